@@ -1,0 +1,190 @@
+#!/usr/bin/env python3
+"""Benchmark of the Parareal-over-stencils hot path on one MI355X.
+
+One step = one pass of the whole hot path over the synthetic workload:
+  * the serial fine reference u_fine = F_{P-1}(...F_0(u0)) (batched sweep kernel, batch 1)
+  * the Parareal solve: start-up coarse run, K iterations of {batched F over all
+    slices, coarse chain + FP64 correction + inter-iterate norms}, and the
+    defect d^k against u_fine every iteration.
+Inputs are resident in HBM before the timed region.  The JSON line reports the
+fine-sweep GLUP/s of the whole step (fine lattice updates / wall time), the
+roofline of the fused RK4 kernel measured with HIP events on the solve's
+stream, the oracle's CPU rate on a bounded sample, and time-to-solution of the
+batched solve against plain per-slice FP64 Parareal and serial FP64 fine.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--config c2_128_fp64]
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+
+
+def log(*a):
+    print("[bench]", *a, file=sys.stderr, flush=True)
+
+
+def cpu_baseline(p, u0_np, budget_s=15.0):
+    """Time the FP64 oracle's RK4 steps on the same grid (bounded sample)."""
+    import oracle
+    oracle.lib()
+    t = time.perf_counter()
+    oracle.fine_steps(p, 0, 1, u0_np)
+    one = time.perf_counter() - t
+    m = int(max(2, min(400, budget_s / max(one, 1e-6))))
+    t = time.perf_counter()
+    oracle.fine_steps(p, 0, m, u0_np)
+    dt = time.perf_counter() - t
+    return {"value": m * p.npts / dt / 1e9, "unit": "GLUP/s", "cores": oracle.threads(), "kind": "oracle",
+            "sample": "%d FP64 RK4 steps of the oracle on one %dx%dx%d field (%.1f s)" % (m, p.n[0], p.n[1], p.n[2],
+                                                                                        dt)}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--config", default="c2_128_fp64")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-compare", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py measures one GPU only: this build has no multi-GPU path (time slices would shard "
+              "over xGMI; see the design notes). Run with --gpus 1.", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+    import paper_1409_8563_amd as pr
+    import workloads as W
+    from paper_1409_8563_amd import costmodel
+
+    if not torch.cuda.is_available():
+        raise SystemExit("bench.py needs a GPU")
+    pr.lib()
+    p, modes = W.config(args.config)
+    mixed = W.MIXED[args.config]
+    sdt = torch.float32 if mixed else torch.float64
+    es = 4 if mixed else 8
+    mode = pr.PR_MODE_MIXED if mixed else pr.PR_MODE_FP64
+    log("config", args.config, "n", p.n, "P", p.P, "K", p.K, "nt_fine", p.nt_fine, "nt_coarse", p.nt_coarse)
+
+    u0_np = W.synth_u0(p.n, modes)
+    u0 = torch.from_numpy(u0_np).cuda()
+    u0s = u0.to(sdt)
+    ufine = torch.empty_like(u0s)
+    ufine64 = torch.empty_like(u0)
+    uT = torch.empty_like(u0)
+    plan = pr.Plan([p], mode | pr.PR_MODE_TIMED)
+    torch.cuda.synchronize()
+
+    def step():
+        pr.fine_sweep(p, u0s, 0, p.nt_fine, u_out=ufine)          # serial fine reference
+        ref = ufine if not mixed else ufine64.copy_(ufine)
+        _, lg = plan.solve([u0], uT=[uT], ref=[ref])
+        return lg
+
+    for i in range(args.warmup):
+        step()
+        log("warmup", i + 1, "done")
+    torch.cuda.synchronize()
+    fine_ms = launches = 0.0
+    t0 = time.perf_counter()
+    for i in range(args.steps):
+        lg = step()
+        tm = plan.timings()
+        fine_ms += tm["fine_ms"]
+        launches += tm["fine_launches"]
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    ms_per_step = (t1 - t0) * 1e3 / args.steps
+    log("timed %d steps: %.2f ms/step" % (args.steps, ms_per_step))
+
+    n3 = p.npts
+    skip = bool(p.flags & W.SKIP_CONVERGED)
+    fine_slices = sum((p.P - k) if skip else p.P for k in range(p.K))
+    fine_lups = fine_slices * p.nf * n3 + p.nt_fine * n3
+    value = fine_lups / (ms_per_step / 1e3) / 1e9
+
+    # dominant kernel: the fused RK4 step over all slices of one iteration
+    avg_launch_s = fine_ms / 1e3 / max(launches, 1)
+    lups_per_launch = fine_slices * p.nf * n3 / max(launches / args.steps, 1)
+    bytes_per_launch = 2 * es * lups_per_launch
+    achieved = bytes_per_launch / avg_launch_s / 1e9
+    dk = [float(lg[0, k, 8] / lg[0, k, 9]) for k in range(p.K)]
+
+    extra = {}
+    if not args.no_compare:
+        # time-to-solution comparisons (outside the timed region)
+        def timed(fn, reps=2):
+            fn()
+            torch.cuda.synchronize()
+            t = time.perf_counter()
+            for _ in range(reps):
+                fn()
+            torch.cuda.synchronize()
+            return (time.perf_counter() - t) * 1e3 / reps
+
+        u64 = u0
+        out64 = torch.empty_like(u64)
+        t_batched = timed(lambda: plan.solve([u0], uT=[uT], want_log=False))
+        plan_ps = pr.Plan([p], pr.PR_MODE_FP64 | pr.PR_MODE_PER_SLICE)
+        t_plain = timed(lambda: plan_ps.solve([u0], uT=[uT], want_log=False))
+        del plan_ps
+        t_serial = timed(lambda: pr.fine_sweep(p, u64, 0, p.nt_fine, u_out=out64))
+        t_coarse = timed(lambda: pr.coarse_sweep(p, u64, 0, p.nt_coarse, u_out=out64))
+        tau = (t_coarse / p.nt_coarse) / (t_serial / p.nt_fine)
+        extra = {
+            "time_to_solution_ms": {"parareal_batched": round(t_batched, 3),
+                                    "parareal_plain_fp64_per_slice": round(t_plain, 3),
+                                    "serial_fine_fp64": round(t_serial, 3)},
+            "batched_vs_plain_fp64_speedup": round(t_plain / t_batched, 3),
+            "tau_c_over_tau_f_fp64_serial": round(tau, 4),
+            "S_bound_eq_speedup": round(costmodel.speedup_bound(p.P, p.K, p.nc / p.nf, tau), 3),
+        }
+        log("comparisons", extra)
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        log("cpu baseline (oracle) ...")
+        cpu = cpu_baseline(p, u0_np)
+        log("cpu baseline", cpu)
+
+    line = {
+        "metric": "fine-sweep GLUP/s + % peak HBM GB/s; Parareal time-to-solution vs plain FP64",
+        "value": round(value, 3),
+        "unit": "GLUP/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_per_step, 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32" if mixed else "f64",
+        "data": "synthetic",
+        "config": {"workload": "%s: %dx%dx%d periodic advection-diffusion, P=%d slices, K=%d, %d fine RK4 / %d "
+                               "coarse Euler steps, %s" % (args.config, p.n[0], p.n[1], p.n[2], p.P, p.K,
+                                                           p.nt_fine, p.nt_coarse,
+                                                           "FP32 sweeps + FP64 correction" if mixed else "FP64"),
+                   "grid": list(p.n), "P": p.P, "K": p.K, "nt_fine": p.nt_fine, "nt_coarse": p.nt_coarse},
+        "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                     "kernel": "rk4_step_fused", "avg_launch_us": round(avg_launch_s * 1e6, 2),
+                     "algorithmic_bytes_per_launch": int(bytes_per_launch)},
+        "cpu_baseline": cpu,
+        "defect_dk": [float("%.3e" % d) for d in dk],
+    }
+    line.update(extra)
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -67,6 +67,7 @@ def lib():
         L.or_serial_coarse.argtypes = [pp, _dp, _dp, _dp]
         L.or_parareal.argtypes = [pp, ctypes.c_int, _dp, _dp, _dp, _dp]
         L.or_norms.argtypes = [ctypes.c_long, _dp, _dp, _dp]
+        L.or_threads.restype = ctypes.c_int
         for f in ("or_rk4_step_alloc", "or_euler_step_alloc", "or_fine_steps", "or_coarse_steps",
                   "or_serial_fine", "or_serial_coarse", "or_parareal"):
             getattr(L, f).restype = ctypes.c_int
@@ -93,6 +94,11 @@ def _field(p, u) -> np.ndarray:
     u = np.ascontiguousarray(u, dtype=np.float64)
     assert u.size == nx * ny * nz
     return u.reshape(nz, ny, nx)
+
+
+def threads() -> int:
+    """OpenMP threads used by the oracle's z loops."""
+    return int(lib().or_threads())
 
 
 def nu(p, t: float) -> float:

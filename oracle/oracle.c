@@ -34,6 +34,9 @@
  * count, and all reductions are serial, so results do not depend on it.
  */
 #include <math.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
 #include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
@@ -49,6 +52,16 @@ typedef struct {
     int32_t nt_coarse;    /* coarse steps on [0, T] */
     int32_t nu_frozen;    /* 1: nu(t_j) for all four RK4 stages */
 } or_prob;
+
+/* Threads the z loops run on (1 without OpenMP). */
+int or_threads(void)
+{
+#ifdef _OPENMP
+    return omp_get_max_threads();
+#else
+    return 1;
+#endif
+}
 
 static long npts_of(const or_prob *p) { return (long)p->nx * p->ny * p->nz; }
 

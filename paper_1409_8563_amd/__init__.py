@@ -1,0 +1,213 @@
+"""Parareal over 3D advection-diffusion stencils on MI355X (gfx950).
+
+Python face of libpr.so (include/pr.h): the fine propagator F (RK4), the
+coarse propagator G (Euler, upwind), the Parareal correction, the defect
+norms and the batched Parareal solve.  All computation happens in the HIP
+library; this module passes torch tensors' device pointers and streams.
+The functions raise ImportError if the library was not built and
+``PrError`` for any non-OK status.
+"""
+from __future__ import annotations
+
+import ctypes
+
+from . import _lib as L
+from ._lib import (PR_ALLOW_UNSTABLE, PR_EARLY_STOP, PR_FP32, PR_FP64, PR_MODE_FP64,  # noqa: F401
+                   PR_MODE_GRAPH, PR_MODE_MIXED, PR_MODE_PER_SLICE, PR_MODE_TIMED, PR_NU_FROZEN,
+                   PR_SKIP_CONVERGED, PrError, check, lib, to_struct)
+
+__all__ = ["fine_sweep", "coarse_sweep", "parareal_update", "defect_norm", "Plan", "check_stability",
+           "set_kernel_variant", "variants", "autotune", "PrError", "lib"]
+
+
+def _torch():
+    import torch
+    return torch
+
+
+def _stream_ptr(stream=None):
+    torch = _torch()
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return ctypes.c_void_p(int(stream.cuda_stream))
+
+
+def _code(t) -> int:
+    torch = _torch()
+    if t.dtype == torch.float64:
+        return PR_FP64
+    if t.dtype == torch.float32:
+        return PR_FP32
+    raise TypeError("fields must be float32 or float64, got %s" % t.dtype)
+
+
+def _dev(t):
+    if not t.is_cuda:
+        raise ValueError("tensor must live on the GPU")
+    if not t.is_contiguous():
+        raise ValueError("tensor must be contiguous")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def _workspace(nbytes, device):
+    torch = _torch()
+    return torch.empty(max(int(nbytes), 1), dtype=torch.uint8, device=device)
+
+
+def _sweep(fn, prob, u_in, step0, nsteps, u_out, stream):
+    torch = _torch()
+    s = to_struct(prob)
+    nx, ny, nz = (int(v) for v in prob.n)
+    npts = nx * ny * nz
+    if u_in.numel() % npts:
+        raise ValueError("u_in size is not a multiple of the grid size")
+    batch = u_in.numel() // npts
+    if u_out is None:
+        u_out = torch.empty_like(u_in)
+    steps = (ctypes.c_int64 * batch)(*([int(step0)] * batch if isinstance(step0, int) else [int(v) for v in step0]))
+    dt = _code(u_in)
+    ws = _workspace(lib().pr_sweep_workspace_bytes(ctypes.byref(s), dt, batch), u_in.device)
+    check(fn(ctypes.byref(s), dt, batch, _dev(u_in), _dev(u_out), steps, int(nsteps),
+             ctypes.c_void_p(ws.data_ptr()), ws.numel(), _stream_ptr(stream)))
+    return u_out
+
+
+def fine_sweep(prob, u_in, step0, nsteps, u_out=None, stream=None):
+    """nsteps RK4 steps of F on every field of u_in (shape [..., nz, ny, nx]);
+    step0 is the global fine step index of the first step (int or one per field)."""
+    return _sweep(lib().pr_fine_sweep, prob, u_in, step0, nsteps, u_out, stream)
+
+
+def coarse_sweep(prob, u_in, step0, nsteps, u_out=None, stream=None):
+    """nsteps forward Euler / upwind steps of G (Algorithm 2)."""
+    return _sweep(lib().pr_coarse_sweep, prob, u_in, step0, nsteps, u_out, stream)
+
+
+def parareal_update(f_new, g_new, g_old, u_out=None, u_out_lo=None, stream=None):
+    """u_out = f_new + (g_new - g_old) in FP64; optional rounded copy u_out_lo."""
+    torch = _torch()
+    if u_out is None:
+        u_out = torch.empty(f_new.shape, dtype=torch.float64, device=f_new.device)
+    check(lib().pr_parareal_update(f_new.numel(), 1, _code(f_new), _dev(f_new), _dev(g_new), _dev(g_old),
+                                   _dev(u_out), _dev(u_out_lo) if u_out_lo is not None else None,
+                                   _stream_ptr(stream)))
+    return u_out
+
+
+def defect_norm(x, ref, batch=1, stream=None):
+    """Device tensor [batch, 4]: max|x-r|, max|r|, sum (x-r)^2, sum r^2."""
+    torch = _torch()
+    n = x.numel() // batch
+    out = torch.empty((batch, 4), dtype=torch.float64, device=x.device)
+    ws = _workspace(lib().pr_defect_workspace_bytes(batch), x.device)
+    check(lib().pr_defect_norm(n, batch, _code(x), _dev(x), _code(ref), _dev(ref), _dev(out),
+                               ctypes.c_void_p(ws.data_ptr()), ws.numel(), _stream_ptr(stream)))
+    return out
+
+
+def check_stability(prob):
+    """(status, fine_margin, coarse_margin); margins <= 1 are stable."""
+    s = to_struct(prob)
+    fm, cm = ctypes.c_double(0), ctypes.c_double(0)
+    rc = lib().pr_check_stability(ctypes.byref(s), ctypes.byref(fm), ctypes.byref(cm))
+    return rc, fm.value, cm.value
+
+
+def set_kernel_variant(fine=0, coarse=0):
+    check(lib().pr_set_kernel_variant(int(fine), int(coarse)))
+
+
+def variants(which):
+    """List of dicts describing the fused variants of F (which=0) or G (which=1)."""
+    out = []
+    for v in range(2, lib().pr_kernel_variant_count(which)):
+        vals = [ctypes.c_int32() for _ in range(6)]
+        check(lib().pr_kernel_variant_info(which, v, *[ctypes.byref(x) for x in vals]))
+        out.append(dict(index=v, name=lib().pr_kernel_variant_name(which, v).decode(), dtype=vals[0].value,
+                        order=vals[1].value, tile=(vals[2].value, vals[3].value), nxp=vals[4].value,
+                        steps=vals[5].value))
+    return out
+
+
+def autotune(prob, dtype, batch, which, stream=None):
+    torch = _torch()
+    s = to_struct(prob)
+    nb = lib().pr_autotune_workspace_bytes(ctypes.byref(s), dtype, batch)
+    ws = _workspace(nb, torch.device("cuda"))
+    best = ctypes.c_int32(0)
+    check(lib().pr_autotune(ctypes.byref(s), dtype, batch, which, ctypes.c_void_p(ws.data_ptr()), ws.numel(),
+                            _stream_ptr(stream), ctypes.byref(best)))
+    return best.value
+
+
+class Plan:
+    """A validated batched Parareal solve over one or more problem instances."""
+
+    def __init__(self, probs, mode=PR_MODE_FP64, device=None):
+        torch = _torch()
+        if not isinstance(probs, (list, tuple)):
+            probs = [probs]
+        self.probs = list(probs)
+        self.mode = int(mode)
+        self._arr = (L.PrProblem * len(probs))(*[to_struct(p) for p in probs])
+        nb = lib().pr_plan_workspace_bytes(self._arr, len(probs), self.mode)
+        if nb == 0:
+            # reproduce the validation error
+            h = ctypes.c_void_p()
+            check(lib().pr_plan_create(self._arr, len(probs), self.mode, None, 0, ctypes.byref(h)))
+        self.ws = _workspace(nb, device or torch.device("cuda"))
+        self._h = ctypes.c_void_p()
+        check(lib().pr_plan_create(self._arr, len(probs), self.mode, ctypes.c_void_p(self.ws.data_ptr()),
+                                   self.ws.numel(), ctypes.byref(self._h)))
+
+    def solve(self, u0, uT=None, ref=None, want_log=True, stream=None):
+        """u0: list of FP64 device tensors (one per instance).  Returns (uT list,
+        log numpy [ninst, K, 12] or None).  Blocking."""
+        import numpy as np
+        torch = _torch()
+        n = len(self.probs)
+        if uT is None:
+            uT = [torch.empty_like(x) for x in u0]
+        for x in list(u0) + list(uT) + (list(ref) if ref is not None else []):
+            if x.dtype != torch.float64:
+                raise TypeError("u0, uT and ref must be float64")
+        pu0 = (ctypes.c_void_p * n)(*[x.data_ptr() for x in u0])
+        puT = (ctypes.c_void_p * n)(*[x.data_ptr() for x in uT])
+        pref = (ctypes.c_void_p * n)(*[x.data_ptr() for x in ref]) if ref is not None else None
+        K = int(self.probs[0].K)
+        log = np.zeros((n, max(K, 1), 12)) if want_log else None
+        lp = log.ctypes.data_as(ctypes.POINTER(ctypes.c_double)) if want_log else None
+        rc = lib().pr_parareal_solve(self._h, pu0, puT, pref, lp, _stream_ptr(stream))
+        check(rc)
+        if want_log:
+            log = log[:, :K]
+        return uT, log
+
+    def iterations(self):
+        return lib().pr_plan_iterations(self._h)
+
+    def timings(self):
+        out = (ctypes.c_double * 6)()
+        check(lib().pr_plan_timings(self._h, out))
+        return dict(fine_ms=out[0], coarse_chain_ms=out[1], init_ms=out[2], fine_launches=out[3],
+                    coarse_launches=out[4], total_ms=out[5])
+
+    def slice_state(self, inst, n):
+        """FP64 tensor view (no copy) of the current U_n of instance `inst`."""
+        torch = _torch()
+        p = ctypes.c_void_p()
+        check(lib().pr_plan_slice_state(self._h, int(inst), int(n), ctypes.byref(p)))
+        nx, ny, nz = (int(v) for v in self.probs[inst].n)
+        off = p.value - self.ws.data_ptr()
+        return self.ws[off:off + nx * ny * nz * 8].view(torch.float64).view(nz, ny, nx)
+
+    def close(self):
+        if getattr(self, "_h", None) and self._h.value:
+            lib().pr_plan_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -1,0 +1,1295 @@
+// Host runtime and C ABI of the Parareal-over-stencils library (gfx950).
+//
+// Responsibilities: argument validation and the stability guard (before any
+// device work), tile layout of the stencil launches, descriptor tables,
+// workspace layout, the Parareal orchestration of Algorithm 1 with all time
+// slices of all instances batched on one device, optional HIP-graph replay,
+// event timing, and the autotuner of the fused kernel variants.
+#include "pr.h"
+#include "pr_internal.h"
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <complex>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <mutex>
+#include <string>
+#include <tuple>
+#include <vector>
+
+using pr::ItemDesc;
+using pr::PointItem;
+using pr::VariantInfo;
+
+namespace {
+
+thread_local std::string g_err = "no error";
+
+int fail(int code, const char *fmt, ...)
+{
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_err = buf;
+    return code;
+}
+
+#define HIPCHK(expr)                                                                                   \
+    do {                                                                                               \
+        hipError_t e_ = (expr);                                                                        \
+        if (e_ != hipSuccess) return fail(PR_EDEVICE, "%s failed: %s", #expr, hipGetErrorString(e_)); \
+    } while (0)
+
+int g_fine_forced = 0, g_coarse_forced = 0;
+std::mutex g_tune_mu;
+std::map<std::tuple<int, int, int, int, int, int>, int> g_tuned;  // (which, nx, ny, nz, dtype, order) -> variant
+
+int g_num_cus = 0;
+
+int device_ready()
+{
+    int n = 0;
+    hipError_t e = hipGetDeviceCount(&n);
+    if (e != hipSuccess || n <= 0) return fail(PR_EDEVICE, "no HIP device available (%s)", hipGetErrorString(e));
+    if (g_num_cus == 0) {
+        int dev = 0;
+        HIPCHK(hipGetDevice(&dev));
+        hipDeviceProp_t prop;
+        HIPCHK(hipGetDeviceProperties(&prop, dev));
+        g_num_cus = prop.multiProcessorCount > 0 ? prop.multiProcessorCount : 256;
+    }
+    return PR_OK;
+}
+
+size_t esize(int dtype) { return dtype == PR_FP64 ? 8 : 4; }
+size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+int64_t npts_of(const pr_problem &p) { return (int64_t)p.n[0] * p.n[1] * p.n[2]; }
+
+// ---- validation -----------------------------------------------------------
+
+int validate_problem(const pr_problem *p, bool need_parareal)
+{
+    if (!p) return fail(PR_EINVAL, "problem is NULL");
+    const int minn = p->fine_order == 4 ? 5 : 3;
+    for (int d = 0; d < 3; ++d) {
+        if (p->n[d] < minn) return fail(PR_EINVAL, "n[%d] = %d < %d", d, p->n[d], minn);
+        if (p->n[d] > 65536) return fail(PR_EINVAL, "n[%d] = %d too large", d, p->n[d]);
+        if (!std::isfinite(p->a[d])) return fail(PR_EINVAL, "a[%d] not finite", d);
+    }
+    if (npts_of(*p) >= ((int64_t)1 << 31)) return fail(PR_EINVAL, "field of %lld points exceeds 2^31 - 1",
+                                                       (long long)npts_of(*p));
+    if (p->fine_order != 2 && p->fine_order != 4) return fail(PR_EINVAL, "fine_order must be 2 or 4");
+    if (!(p->nu0 > 0.0) || !std::isfinite(p->nu0)) return fail(PR_EINVAL, "nu0 must be positive and finite");
+    if (!std::isfinite(p->nu_amp) || !(std::fabs(p->nu_amp) < 1.0))
+        return fail(PR_EINVAL, "|nu_amp| must be < 1 so that nu(t) > 0");
+    if (!std::isfinite(p->nu_omega)) return fail(PR_EINVAL, "nu_omega not finite");
+    if (!(p->T > 0.0) || !std::isfinite(p->T)) return fail(PR_EINVAL, "T must be positive and finite");
+    if (p->nt_fine < 1 || p->nt_coarse < 1) return fail(PR_EINVAL, "step counts must be >= 1");
+    if (need_parareal) {
+        if (p->P < 1) return fail(PR_EINVAL, "P must be >= 1");
+        if (p->nt_fine % p->P != 0) return fail(PR_EINVAL, "nt_fine = %d is not a multiple of P = %d", p->nt_fine, p->P);
+        if (p->nt_coarse % p->P != 0)
+            return fail(PR_EINVAL, "nt_coarse = %d is not a multiple of P = %d", p->nt_coarse, p->P);
+        if (p->K < 0 || p->K > p->P) return fail(PR_EINVAL, "K = %d outside [0, P = %d]", p->K, p->P);
+        if ((p->flags & PR_EARLY_STOP) && !(p->tol >= 0.0)) return fail(PR_EINVAL, "tol must be >= 0");
+    }
+    if (p->flags & ~(PR_NU_FROZEN | PR_ALLOW_UNSTABLE | PR_EARLY_STOP | PR_SKIP_CONVERGED))
+        return fail(PR_EINVAL, "unknown flag bits 0x%x", p->flags);
+    return PR_OK;
+}
+
+// ---- stability ------------------------------------------------------------
+
+void margins(const pr_problem &p, double *fm, double *cm)
+{
+    const double numax = p.nu0 * (1.0 + std::fabs(p.nu_amp));
+    const double numin = p.nu0 * (1.0 - std::fabs(p.nu_amp));
+    double sa = 0.0, sd = 0.0;
+    for (int d = 0; d < 3; ++d) {
+        sa += std::fabs(p.a[d]) * p.n[d];
+        sd += (double)p.n[d] * p.n[d];
+    }
+    const double Dt = p.T / p.nt_coarse;
+    *cm = Dt * (sa + 2.0 * numax * sd);
+
+    const double dt = p.T / p.nt_fine;
+    constexpr int NS = 48;
+    double th[NS];
+    for (int i = 0; i < NS; ++i) th[i] = M_PI * i / (NS - 1);
+    // per-axis symbol parts: diffusion sd_d(theta) * n_d^2 and advection sa_d(theta) * n_d
+    std::vector<double> D[3], A[3];
+    for (int d = 0; d < 3; ++d) {
+        D[d].resize(NS);
+        A[d].resize(NS);
+        const double n = p.n[d];
+        for (int i = 0; i < NS; ++i) {
+            const double t = th[i];
+            if (p.fine_order == 4) {
+                D[d][i] = (-2.0 * std::cos(2 * t) + 32.0 * std::cos(t) - 30.0) / 12.0 * n * n;
+                A[d][i] = -p.a[d] * (8.0 * std::sin(t) - std::sin(2 * t)) / 6.0 * n;
+            } else {
+                D[d][i] = (2.0 * std::cos(t) - 2.0) * n * n;
+                A[d][i] = -p.a[d] * std::sin(t) * n;
+            }
+        }
+    }
+    double worst = 0.0;
+    const double nus[2] = {numin, numax};
+    for (double nu : nus)
+        for (int i = 0; i < NS; ++i)
+            for (int j = 0; j < NS; ++j)
+                for (int k = 0; k < NS; ++k) {
+                    const std::complex<double> z(dt * nu * (D[0][i] + D[1][j] + D[2][k]),
+                                                 dt * (A[0][i] + A[1][j] + A[2][k]));
+                    const std::complex<double> R = 1.0 + z * (1.0 + z * (0.5 + z * (1.0 / 6.0 + z / 24.0)));
+                    worst = std::max(worst, std::abs(R));
+                }
+    *fm = worst;
+}
+
+int stability_guard(const pr_problem &p, bool fine, bool coarse)
+{
+    if (p.flags & PR_ALLOW_UNSTABLE) return PR_OK;
+    double fm = 0, cm = 0;
+    margins(p, &fm, &cm);
+    if (fine && fm > 1.0 + 1e-12)
+        return fail(PR_EUNSTABLE, "fine RK4 step unstable: max |R(dt mu)| = %.6g > 1", fm);
+    if (coarse && cm > 1.0 + 1e-12)
+        return fail(PR_EUNSTABLE,
+                    "coarse Euler/upwind step unstable: Dt*(sum|a|/h + 2 nu_max sum 1/h^2) = %.6g > 1 "
+                    "(raise nt_coarse or set PR_ALLOW_UNSTABLE)",
+                    cm);
+    return PR_OK;
+}
+
+// ---- variants and layout ---------------------------------------------------
+
+int find_fine(const char *name)
+{
+    for (int v = 2; v < pr::fine_variant_count(); ++v)
+        if (!std::strcmp(pr::fine_variant(v)->name, name)) return v;
+    return -1;
+}
+int find_coarse(const char *name)
+{
+    for (int v = 2; v < pr::coarse_variant_count(); ++v)
+        if (!std::strcmp(pr::coarse_variant(v)->name, name)) return v;
+    return -1;
+}
+
+bool fine_applicable(int v, int dtype, int order, const pr_problem &p)
+{
+    if (v == 1) return true;
+    const VariantInfo *vi = pr::fine_variant(v);
+    return vi && vi->dtype == dtype && vi->order == order && p.n[0] % vi->nxp == 0;
+}
+bool coarse_applicable(int v, int dtype, const pr_problem &p)
+{
+    if (v == 1) return true;
+    const VariantInfo *vi = pr::coarse_variant(v);
+    return vi && vi->dtype == dtype && p.n[0] % vi->nxp == 0;
+}
+
+int pick_fine_default(const pr_problem &p, int dtype)
+{
+    const int order = p.fine_order;
+    const bool even = p.n[0] % 2 == 0;
+    const char *name;
+    if (dtype == PR_FP64)
+        name = order == 4 ? (even ? "rk4_f64_o4_t32x16_p2x1" : "rk4_f64_o4_t24x8_p1x1")
+                          : (even ? "rk4_f64_o2_t32x32_p2x2" : "rk4_f64_o2_t32x32_p1x4");
+    else
+        name = order == 4 ? (even ? "rk4_f32_o4_t32x16_p2x2" : "rk4_f32_o4_t32x16_p1x2")
+                          : (even ? "rk4_f32_o2_t64x32_p2x4" : "rk4_f32_o2_t32x32_p1x4");
+    return find_fine(name);
+}
+
+int pick_fine(const pr_problem &p, int dtype)
+{
+    if (g_fine_forced) return g_fine_forced;
+    {
+        std::lock_guard<std::mutex> lk(g_tune_mu);
+        auto it = g_tuned.find({0, p.n[0], p.n[1], p.n[2], dtype, p.fine_order});
+        if (it != g_tuned.end()) return it->second;
+    }
+    return pick_fine_default(p, dtype);
+}
+
+int pick_coarse_default(const pr_problem &p, int dtype)
+{
+    const bool even = p.n[0] % 2 == 0;
+    const char *name = dtype == PR_FP64 ? (even ? "euler4_f64_t32x32_p2x2" : "euler4_f64_t32x32_p1x4")
+                                        : (even ? "euler4_f32_t32x32_p2x2" : "euler4_f32_t32x32_p1x4");
+    return find_coarse(name);
+}
+
+int pick_coarse(const pr_problem &p, int dtype)
+{
+    if (g_coarse_forced) return g_coarse_forced;
+    {
+        std::lock_guard<std::mutex> lk(g_tune_mu);
+        auto it = g_tuned.find({1, p.n[0], p.n[1], p.n[2], dtype, 0});
+        if (it != g_tuned.end()) return it->second;
+    }
+    return pick_coarse_default(p, dtype);
+}
+
+constexpr int kRefThreads = 256;
+
+// Fill geometry, physics and tile layout of one sweep item (not pointers).
+void fill_item(ItemDesc &it, const pr_problem &p, bool fine)
+{
+    it.nx = p.n[0];
+    it.ny = p.n[1];
+    it.nz = p.n[2];
+    it.dt = fine ? p.T / p.nt_fine : p.T / p.nt_coarse;
+    it.nu0 = p.nu0;
+    it.nu_amp = p.nu_amp;
+    it.nu_omega = p.nu_omega;
+    for (int d = 0; d < 3; ++d) {
+        it.inv_h2[d] = (double)p.n[d] * p.n[d];
+        it.a_over_h[d] = p.a[d] * p.n[d];
+    }
+    it.frozen = (fine && (p.flags & PR_NU_FROZEN)) ? 1 : 0;
+}
+
+// Tile layout of a set of items for a variant; block ranges are assigned in
+// item order.  Returns the total number of blocks.
+int layout(std::vector<ItemDesc> &items, const VariantInfo *vi, bool ref, int zmin)
+{
+    const int target = 4 * std::max(g_num_cus, 1);
+    if (ref) {
+        int b = 0;
+        for (auto &it : items) {
+            const int64_t n = (int64_t)it.nx * it.ny * it.nz;
+            it.tiles_x = it.tiles_y = it.zchunks = 1;
+            it.tz = it.nz;
+            it.nblocks = (int)((n + kRefThreads - 1) / kRefThreads);
+            it.block_begin = b;
+            b += it.nblocks;
+        }
+        return b;
+    }
+    int64_t bxy = 0;
+    for (auto &it : items) {
+        it.tiles_x = (it.nx + vi->tx - 1) / vi->tx;
+        it.tiles_y = (it.ny + vi->ty - 1) / vi->ty;
+        bxy += (int64_t)it.tiles_x * it.tiles_y;
+    }
+    int want = (int)std::max<int64_t>(1, (target + bxy - 1) / std::max<int64_t>(bxy, 1));
+    int b = 0;
+    for (auto &it : items) {
+        const int maxz = std::max(1, it.nz / zmin);
+        const int zc = std::min(want, maxz);
+        it.tz = (it.nz + zc - 1) / zc;
+        it.zchunks = (it.nz + it.tz - 1) / it.tz;
+        it.nblocks = it.tiles_x * it.tiles_y * it.zchunks;
+        it.block_begin = b;
+        b += it.nblocks;
+    }
+    return b;
+}
+
+const VariantInfo *fine_info(int v) { return v >= 2 ? pr::fine_variant(v) : nullptr; }
+const VariantInfo *coarse_info(int v) { return v >= 2 ? pr::coarse_variant(v) : nullptr; }
+int coarse_steps_per_launch(int v) { return v >= 2 ? pr::coarse_variant(v)->steps : 1; }
+
+// ---- sweeps -----------------------------------------------------------------
+
+size_t sweep_ws(const pr_problem &p, int dtype, int batch, bool fine_ref)
+{
+    const size_t states = (size_t)batch * npts_of(p) * esize(dtype);
+    return align256((size_t)batch * sizeof(ItemDesc)) + align256(states) + (fine_ref ? 3 * align256(states) : 0);
+}
+
+int sweep_common(const pr_problem *prob, int dtype, int batch, const void *u_in, void *u_out, const int64_t *step0,
+                 int nsteps, void *ws, size_t ws_bytes, void *stream, bool fine)
+{
+    int rc = validate_problem(prob, false);
+    if (rc) return rc;
+    if (dtype != PR_FP32 && dtype != PR_FP64) return fail(PR_EINVAL, "dtype must be PR_FP32 or PR_FP64");
+    if (batch < 1) return fail(PR_EINVAL, "batch must be >= 1");
+    if (nsteps < 0) return fail(PR_EINVAL, "nsteps must be >= 0");
+    if (!u_in || !u_out) return fail(PR_EINVAL, "u_in/u_out is NULL");
+    if (!step0) return fail(PR_EINVAL, "step0 is NULL");
+    for (int b = 0; b < batch; ++b)
+        if (step0[b] < 0) return fail(PR_EINVAL, "step0[%d] < 0", b);
+    const size_t bytes = (size_t)batch * npts_of(*prob) * esize(dtype);
+    const char *a = (const char *)u_in, *o = (const char *)u_out;
+    if (((uintptr_t)a | (uintptr_t)o) & 15) return fail(PR_EINVAL, "u_in/u_out must be 16-byte aligned");
+    if (a < o + bytes && o < a + bytes) return fail(PR_EINVAL, "u_in and u_out overlap");
+    rc = stability_guard(*prob, fine, !fine);
+    if (rc) return rc;
+    int v = fine ? pick_fine(*prob, dtype) : pick_coarse(*prob, dtype);
+    if (v < 1) return fail(PR_EUNSUPPORTED, "no kernel variant for this problem");
+    if (fine ? !fine_applicable(v, dtype, prob->fine_order, *prob) : !coarse_applicable(v, dtype, *prob))
+        return fail(PR_EUNSUPPORTED, "selected kernel variant %d does not apply to this dtype/order/n_x", v);
+    const bool ref = (v == 1);
+    const size_t need = sweep_ws(*prob, dtype, batch, fine && ref);
+    if (!ws || ws_bytes < need) return fail(PR_ENOMEM, "workspace of %zu bytes < %zu needed", ws_bytes, need);
+    rc = device_ready();
+    if (rc) return rc;
+    hipStream_t s = (hipStream_t)stream;
+    if (nsteps == 0) {
+        HIPCHK(hipMemcpyAsync(u_out, u_in, bytes, hipMemcpyDeviceToDevice, s));
+        return PR_OK;
+    }
+    char *w = (char *)ws;
+    ItemDesc *table = (ItemDesc *)w;
+    char *tmp = w + align256((size_t)batch * sizeof(ItemDesc));
+    char *scr = tmp + align256(bytes);
+    const size_t fb = (size_t)npts_of(*prob) * esize(dtype);
+    std::vector<ItemDesc> items(batch);
+    for (int b = 0; b < batch; ++b) {
+        ItemDesc &it = items[b];
+        std::memset(&it, 0, sizeof it);
+        fill_item(it, *prob, fine);
+        it.src0 = a + b * fb;
+        it.dst = (char *)u_out + b * fb;
+        it.tmp = tmp + b * fb;
+        it.scratch = scr + 3 * b * fb;
+        it.step0 = step0[b];
+        it.nsteps = nsteps;
+    }
+    const VariantInfo *vi = fine ? fine_info(v) : coarse_info(v);
+    const int zmin = fine ? 8 : 4;
+    const int nblocks = layout(items, vi, ref, zmin);
+    HIPCHK(pr::launch_write_items(items.data(), batch, table, s));
+    if (fine) {
+        for (int j = 0; j < nsteps; ++j)
+            HIPCHK(pr::launch_fine_step(v, dtype, prob->fine_order, table, batch, nblocks, j, s));
+    } else {
+        const int S = coarse_steps_per_launch(v);
+        const int nch = (nsteps + S - 1) / S;
+        for (int c = 0; c < nch; ++c) HIPCHK(pr::launch_coarse_chunk(v, dtype, table, batch, nblocks, c, s));
+    }
+    return PR_OK;
+}
+
+}  // namespace
+
+// ===========================================================================
+// Plans
+// ===========================================================================
+
+struct pr_plan {
+    int ninst = 0;
+    int mode = 0;
+    int dtype = PR_FP64;  // sweep dtype
+    int K = 0;
+    uint32_t flags = 0;
+    int fine_v = 0, coarse_v = 0;
+    bool mixed = false, per_slice = false, graph = false, timed = false, skip = false, early = false;
+    std::vector<pr_problem> probs;
+    int Pmax = 0;
+
+    struct Inst {
+        int64_t npts;
+        int P, nf, nc;
+        double *U;                 // (P+1) FP64 states
+        char *Ulo;                 // (P+1) sweep states (== U in FP64 mode)
+        char *Fv, *Ftmp, *Gold[2], *Gtmp, *Fscr;
+        double *part;              // P x kNormBlocks x 4 correction partials
+        double *refpart;           // kNormBlocks x 4
+    };
+    std::vector<Inst> inst;
+
+    // device tables
+    ItemDesc *fine_tab = nullptr;       // K tables of nfine[k] items (batched layout)
+    std::vector<int> fine_off, fine_cnt;   // per k: offset into fine_tab, items
+    std::vector<std::vector<int>> fine_active_blocks;  // per k, per step j: blocks of active prefix
+    ItemDesc *slice_tab = nullptr;      // per-slice layout: all (i, n), block_begin = 0
+    std::vector<int> slice_index;       // (i, n) -> index into slice_tab
+    std::vector<int> slice_blocks;      // blocks of each slice_tab item
+    ItemDesc *coarse_tab = nullptr;     // [parity][n] -> up to ninst items
+    std::vector<int> coarse_cnt;        // per n: items (instances with P_i > n)
+    std::vector<int> coarse_blocks;     // per (parity, n)
+    std::vector<int> coarse_nch;        // per n: chunks of the longest item
+    PointItem *pt_assign = nullptr;     // [n][ninst]   init: U_{n+1} = Gold0_n
+    PointItem *pt_corr = nullptr;       // [parity][n][ninst]
+    PointItem *pt_skip = nullptr;       // [parity][n][ninst] b = c = Gold[parity]
+    PointItem *pt_final = nullptr;      // [k][sum P_i] per-slice finals
+    PointItem *io_u0 = nullptr;         // [ninst] written per solve
+    PointItem *io_uT = nullptr;         // [ninst]
+    PointItem *io_ref = nullptr;        // [K][ninst] partials + final
+    double *dlog = nullptr;             // [K][sum P_i][4]
+    double *dlog_ref = nullptr;         // [K][ninst][4]
+    std::vector<int> slice_base;        // per instance: offset of its slices in sum P_i
+    int sumP = 0;
+
+    hipStream_t own = nullptr;
+    hipGraphExec_t exec = nullptr;
+    hipGraph_t graph_h = nullptr;
+    std::vector<hipEvent_t> ev;
+    int iters_done = 0;
+    double timings[6] = {0, 0, 0, 0, 0, 0};
+    bool had_ref_graph = false;
+};
+
+namespace {
+
+struct Layout {
+    size_t total = 0;
+};
+
+// Lay out (or only size) the plan workspace.  With plan == nullptr only the
+// size is computed.
+size_t plan_layout(const pr_problem *probs, int ninst, int mode, char *base, pr_plan *plan)
+{
+    const bool mixed = (mode & 1) != 0;
+    const int dtype = mixed ? PR_FP32 : PR_FP64;
+    const size_t es = esize(dtype);
+    const bool fine_ref = (g_fine_forced == 1);
+    const int K = probs[0].K;
+    size_t off = 0;
+    auto take = [&](size_t bytes) -> char * {
+        char *p = base ? base + off : nullptr;
+        off += align256(bytes);
+        return p;
+    };
+    int sumP = 0, Pmax = 0;
+    for (int i = 0; i < ninst; ++i) {
+        sumP += probs[i].P;
+        Pmax = std::max(Pmax, probs[i].P);
+    }
+    for (int i = 0; i < ninst; ++i) {
+        const pr_problem &p = probs[i];
+        const size_t n = (size_t)npts_of(p);
+        pr_plan::Inst in{};
+        in.npts = (int64_t)n;
+        in.P = p.P;
+        in.nf = p.nt_fine / p.P;
+        in.nc = p.nt_coarse / p.P;
+        in.U = (double *)take((p.P + 1) * n * 8);
+        in.Ulo = mixed ? take((p.P + 1) * n * es) : (char *)in.U;
+        in.Fv = take(p.P * n * es);
+        in.Ftmp = take(p.P * n * es);
+        in.Gold[0] = take(p.P * n * es);
+        in.Gold[1] = take(p.P * n * es);
+        in.Gtmp = take(n * es);
+        in.Fscr = fine_ref ? take(3 * p.P * n * es) : nullptr;
+        in.part = (double *)take((size_t)p.P * pr::kNormBlocks * 4 * 8);
+        in.refpart = (double *)take((size_t)pr::kNormBlocks * 4 * 8);
+        if (plan) plan->inst.push_back(in);
+    }
+    const int Kt = std::max(K, 1);
+    char *fine_tab = take((size_t)Kt * sumP * sizeof(ItemDesc));
+    char *slice_tab = take((size_t)sumP * sizeof(ItemDesc));
+    char *coarse_tab = take((size_t)2 * Pmax * ninst * sizeof(ItemDesc));
+    char *pt_assign = take((size_t)Pmax * ninst * sizeof(PointItem));
+    char *pt_corr = take((size_t)2 * Pmax * ninst * sizeof(PointItem));
+    char *pt_skip = take((size_t)2 * Pmax * ninst * sizeof(PointItem));
+    char *pt_final = take((size_t)Kt * sumP * sizeof(PointItem));
+    char *io_u0 = take((size_t)ninst * sizeof(PointItem));
+    char *io_uT = take((size_t)ninst * sizeof(PointItem));
+    char *io_ref = take((size_t)Kt * ninst * sizeof(PointItem));
+    char *dlog = take((size_t)Kt * sumP * 4 * 8);
+    char *dlog_ref = take((size_t)Kt * ninst * 4 * 8);
+    if (plan) {
+        plan->fine_tab = (ItemDesc *)fine_tab;
+        plan->slice_tab = (ItemDesc *)slice_tab;
+        plan->coarse_tab = (ItemDesc *)coarse_tab;
+        plan->pt_assign = (PointItem *)pt_assign;
+        plan->pt_corr = (PointItem *)pt_corr;
+        plan->pt_skip = (PointItem *)pt_skip;
+        plan->pt_final = (PointItem *)pt_final;
+        plan->io_u0 = (PointItem *)io_u0;
+        plan->io_uT = (PointItem *)io_uT;
+        plan->io_ref = (PointItem *)io_ref;
+        plan->dlog = (double *)dlog;
+        plan->dlog_ref = (double *)dlog_ref;
+        plan->sumP = sumP;
+        plan->Pmax = Pmax;
+    }
+    return off;
+}
+
+int validate_plan_args(const pr_problem *probs, int ninst, int mode)
+{
+    if (!probs) return fail(PR_EINVAL, "probs is NULL");
+    if (ninst < 1) return fail(PR_EINVAL, "ninst must be >= 1");
+    if (mode & ~(PR_MODE_MIXED | PR_MODE_PER_SLICE | PR_MODE_GRAPH | PR_MODE_TIMED))
+        return fail(PR_EINVAL, "unknown mode bits 0x%x", mode);
+    for (int i = 0; i < ninst; ++i) {
+        int rc = validate_problem(&probs[i], true);
+        if (rc) {
+            g_err = "instance " + std::to_string(i) + ": " + g_err;
+            return rc;
+        }
+        if (probs[i].K != probs[0].K) return fail(PR_EINVAL, "K differs between instances");
+        if (probs[i].flags != probs[0].flags) return fail(PR_EINVAL, "flags differ between instances");
+        if (probs[i].tol != probs[0].tol) return fail(PR_EINVAL, "tol differs between instances");
+        rc = stability_guard(probs[i], true, true);
+        if (rc) {
+            g_err = "instance " + std::to_string(i) + ": " + g_err;
+            return rc;
+        }
+    }
+    return PR_OK;
+}
+
+template <typename T>
+int upload(T *dev, const std::vector<T> &host)
+{
+    if (host.empty()) return PR_OK;
+    HIPCHK(hipMemcpy(dev, host.data(), host.size() * sizeof(T), hipMemcpyHostToDevice));
+    return PR_OK;
+}
+
+char *slice_ptr(char *base, int n, int64_t npts, size_t es) { return base + (size_t)n * npts * es; }
+
+int build_tables(pr_plan *pl)
+{
+    const size_t es = esize(pl->dtype);
+    const int ninst = pl->ninst;
+    const int K = pl->K;
+    const VariantInfo *fvi = fine_info(pl->fine_v);
+    const VariantInfo *cvi = coarse_info(pl->coarse_v);
+    const bool fref = pl->fine_v == 1, cref = pl->coarse_v == 1;
+    for (const auto &in : pl->inst)
+        if (fref && !in.Fscr) return fail(PR_EINVAL, "kernel variant changed between workspace query and plan creation");
+
+    pl->slice_base.resize(ninst);
+    for (int i = 0, b = 0; i < ninst; ++i) {
+        pl->slice_base[i] = b;
+        b += pl->inst[i].P;
+    }
+    auto fine_item = [&](int i, int n) {
+        const pr_plan::Inst &in = pl->inst[i];
+        ItemDesc it;
+        std::memset(&it, 0, sizeof it);
+        fill_item(it, pl->probs[i], true);
+        it.src0 = slice_ptr(in.Ulo, n, in.npts, es);
+        it.dst = slice_ptr(in.Fv, n, in.npts, es);
+        it.tmp = slice_ptr(in.Ftmp, n, in.npts, es);
+        it.scratch = in.Fscr ? in.Fscr + (size_t)3 * n * in.npts * es : nullptr;
+        it.step0 = (int64_t)n * in.nf;
+        it.nsteps = in.nf;
+        return it;
+    };
+
+    // batched fine tables, one per iteration (slices n >= k when skipping)
+    std::vector<ItemDesc> all;
+    pl->fine_off.assign(std::max(K, 1), 0);
+    pl->fine_cnt.assign(std::max(K, 1), 0);
+    pl->fine_active_blocks.assign(std::max(K, 1), {});
+    for (int k = 0; k < K; ++k) {
+        std::vector<ItemDesc> items;
+        for (int i = 0; i < ninst; ++i)
+            for (int n = (pl->skip ? k : 0); n < pl->inst[i].P; ++n) items.push_back(fine_item(i, n));
+        std::stable_sort(items.begin(), items.end(),
+                         [](const ItemDesc &a, const ItemDesc &b) { return a.nsteps > b.nsteps; });
+        const int nb = layout(items, fvi, fref, 8);
+        (void)nb;
+        int maxsteps = items.empty() ? 0 : items[0].nsteps;
+        std::vector<int> act(maxsteps, 0);
+        for (int j = 0; j < maxsteps; ++j) {
+            int blocks = 0;
+            for (auto &it : items)
+                if (it.nsteps > j) blocks = it.block_begin + it.nblocks;
+            act[j] = blocks;
+        }
+        pl->fine_active_blocks[k] = act;
+        pl->fine_off[k] = (int)all.size();
+        pl->fine_cnt[k] = (int)items.size();
+        all.insert(all.end(), items.begin(), items.end());
+    }
+    int rc = upload(pl->fine_tab, all);
+    if (rc) return rc;
+
+    // per-slice tables: every (i, n) laid out on its own
+    std::vector<ItemDesc> sl;
+    pl->slice_index.assign(pl->sumP, 0);
+    for (int i = 0; i < ninst; ++i)
+        for (int n = 0; n < pl->inst[i].P; ++n) {
+            std::vector<ItemDesc> one{fine_item(i, n)};
+            layout(one, fvi, fref, 8);
+            pl->slice_index[pl->slice_base[i] + n] = (int)sl.size();
+            pl->slice_blocks.push_back(one[0].nblocks);
+            sl.push_back(one[0]);
+        }
+    rc = upload(pl->slice_tab, sl);
+    if (rc) return rc;
+
+    // coarse tables [parity][n]: instances with P_i > n
+    const int Pmax = pl->Pmax;
+    std::vector<ItemDesc> ct((size_t)2 * Pmax * ninst);
+    pl->coarse_cnt.assign(Pmax, 0);
+    pl->coarse_blocks.assign(2 * Pmax, 0);
+    pl->coarse_nch.assign(Pmax, 0);
+    const int S = coarse_steps_per_launch(pl->coarse_v);
+    for (int par = 0; par < 2; ++par)
+        for (int n = 0; n < Pmax; ++n) {
+            std::vector<ItemDesc> items;
+            for (int i = 0; i < ninst; ++i) {
+                const pr_plan::Inst &in = pl->inst[i];
+                if (n >= in.P) continue;
+                ItemDesc it;
+                std::memset(&it, 0, sizeof it);
+                fill_item(it, pl->probs[i], false);
+                it.src0 = slice_ptr(in.Ulo, n, in.npts, es);
+                it.dst = slice_ptr(in.Gold[par], n, in.npts, es);
+                it.tmp = in.Gtmp;
+                it.step0 = (int64_t)n * in.nc;
+                it.nsteps = in.nc;
+                items.push_back(it);
+            }
+            std::stable_sort(items.begin(), items.end(),
+                             [](const ItemDesc &a, const ItemDesc &b) { return a.nsteps > b.nsteps; });
+            const int nb = layout(items, cvi, cref, 4);
+            pl->coarse_blocks[par * Pmax + n] = nb;
+            pl->coarse_cnt[n] = (int)items.size();
+            pl->coarse_nch[n] = items.empty() ? 0 : (items[0].nsteps + S - 1) / S;
+            for (size_t m = 0; m < items.size(); ++m) ct[((size_t)par * Pmax + n) * ninst + m] = items[m];
+        }
+    rc = upload(pl->coarse_tab, ct);
+    if (rc) return rc;
+
+    // pointwise tables
+    std::vector<PointItem> assign((size_t)Pmax * ninst), corr((size_t)2 * Pmax * ninst),
+        skip((size_t)2 * Pmax * ninst);
+    for (int n = 0; n < Pmax; ++n) {
+        int m = 0;
+        for (int i = 0; i < ninst; ++i) {
+            const pr_plan::Inst &in = pl->inst[i];
+            if (n >= in.P) continue;
+            PointItem a{};
+            a.a = slice_ptr(in.Gold[0], n, in.npts, es);
+            a.u = in.U + (size_t)(n + 1) * in.npts;
+            a.ulo = pl->mixed ? (void *)slice_ptr(in.Ulo, n + 1, in.npts, es) : nullptr;
+            a.npts = in.npts;
+            assign[(size_t)n * ninst + m] = a;
+            for (int par = 0; par < 2; ++par) {
+                // iteration k with k % 2 == par: G_new -> Gold[1-par], G_old = Gold[par]
+                PointItem c{};
+                c.a = slice_ptr(in.Fv, n, in.npts, es);
+                c.b = slice_ptr(in.Gold[1 - par], n, in.npts, es);
+                c.c = slice_ptr(in.Gold[par], n, in.npts, es);
+                c.u = in.U + (size_t)(n + 1) * in.npts;
+                c.ulo = pl->mixed ? (void *)slice_ptr(in.Ulo, n + 1, in.npts, es) : nullptr;
+                c.partials = in.part + (size_t)n * pr::kNormBlocks * 4;
+                c.npts = in.npts;
+                corr[((size_t)par * Pmax + n) * ninst + m] = c;
+                PointItem s = c;
+                s.b = slice_ptr(in.Gold[par], n, in.npts, es);
+                skip[((size_t)par * Pmax + n) * ninst + m] = s;
+            }
+            ++m;
+        }
+    }
+    rc = upload(pl->pt_assign, assign);
+    if (rc) return rc;
+    rc = upload(pl->pt_corr, corr);
+    if (rc) return rc;
+    rc = upload(pl->pt_skip, skip);
+    if (rc) return rc;
+
+    std::vector<PointItem> fin((size_t)std::max(K, 1) * pl->sumP);
+    for (int k = 0; k < K; ++k)
+        for (int i = 0; i < ninst; ++i)
+            for (int n = 0; n < pl->inst[i].P; ++n) {
+                PointItem f{};
+                f.partials = pl->inst[i].part + (size_t)n * pr::kNormBlocks * 4;
+                f.out4 = pl->dlog + ((size_t)k * pl->sumP + pl->slice_base[i] + n) * 4;
+                fin[(size_t)k * pl->sumP + pl->slice_base[i] + n] = f;
+            }
+    return upload(pl->pt_final, fin);
+}
+
+// Enqueue the start-up coarse run of Algorithm 1 (after U_0 is in place).
+int enqueue_init(pr_plan *pl, hipStream_t s)
+{
+    const int ninst = pl->ninst, Pmax = pl->Pmax;
+    for (int n = 0; n < Pmax; ++n) {
+        const int cnt = pl->coarse_cnt[n];
+        if (!cnt) continue;
+        const ItemDesc *tab = pl->coarse_tab + (size_t)(0 * Pmax + n) * ninst;
+        for (int c = 0; c < pl->coarse_nch[n]; ++c)
+            HIPCHK(pr::launch_coarse_chunk(pl->coarse_v, pl->dtype, tab, cnt, pl->coarse_blocks[n], c, s));
+        HIPCHK(pr::launch_pointwise(pr::kOpAssign, pl->dtype, pl->pt_assign + (size_t)n * ninst, cnt, false, s));
+    }
+    return PR_OK;
+}
+
+int enqueue_fine(pr_plan *pl, int k, hipStream_t s)
+{
+    if (!pl->per_slice) {
+        const ItemDesc *tab = pl->fine_tab + pl->fine_off[k];
+        const int cnt = pl->fine_cnt[k];
+        const std::vector<int> &act = pl->fine_active_blocks[k];
+        for (int j = 0; j < (int)act.size(); ++j)
+            HIPCHK(pr::launch_fine_step(pl->fine_v, pl->dtype, pl->probs[0].fine_order, tab, cnt, act[j], j, s));
+    } else {
+        for (int i = 0; i < pl->ninst; ++i)
+            for (int n = (pl->skip ? k : 0); n < pl->inst[i].P; ++n) {
+                const int idx = pl->slice_index[pl->slice_base[i] + n];
+                const ItemDesc *tab = pl->slice_tab + idx;
+                const int nf = pl->inst[i].nf;
+                for (int j = 0; j < nf; ++j)
+                    HIPCHK(pr::launch_fine_step(pl->fine_v, pl->dtype, pl->probs[i].fine_order, tab, 1,
+                                                pl->slice_blocks[idx], j, s));
+            }
+    }
+    return PR_OK;
+}
+
+}  // namespace
+
+namespace {
+
+int enqueue_iteration(pr_plan *pl, int k, hipStream_t s, bool with_ref)
+{
+    const int ninst = pl->ninst, Pmax = pl->Pmax;
+    const int par = k & 1;
+    if (pl->timed) HIPCHK(hipEventRecord(pl->ev[2 + 3 * k], s));
+    int rc = enqueue_fine(pl, k, s);
+    if (rc) return rc;
+    if (pl->timed) HIPCHK(hipEventRecord(pl->ev[3 + 3 * k], s));
+    const int nstart = pl->skip ? k : 0;
+    for (int n = nstart; n < Pmax; ++n) {
+        const int cnt = pl->coarse_cnt[n];
+        if (!cnt) continue;
+        if (pl->skip && n == k) {
+            // G_n(U^{k+1}_n) would equal G_old bitwise: U^{k+1}_{n+1} = F + 0
+            HIPCHK(pr::launch_pointwise(pr::kOpCorrect, pl->dtype, pl->pt_skip + ((size_t)par * Pmax + n) * ninst, cnt,
+                                        true, s));
+            continue;
+        }
+        const int cpar = 1 - par;  // G_new goes to Gold[1 - k%2]
+        const ItemDesc *tab = pl->coarse_tab + ((size_t)cpar * Pmax + n) * ninst;
+        for (int c = 0; c < pl->coarse_nch[n]; ++c)
+            HIPCHK(pr::launch_coarse_chunk(pl->coarse_v, pl->dtype, tab, cnt, pl->coarse_blocks[cpar * Pmax + n], c, s));
+        HIPCHK(pr::launch_pointwise(pr::kOpCorrect, pl->dtype, pl->pt_corr + ((size_t)par * Pmax + n) * ninst, cnt,
+                                    true, s));
+    }
+    HIPCHK(pr::launch_defect_final(pl->pt_final + (size_t)k * pl->sumP, pl->sumP, s));
+    if (with_ref) {
+        HIPCHK(pr::launch_defect_partials(PR_FP64, PR_FP64, pl->io_ref + (size_t)k * ninst, ninst, s));
+        HIPCHK(pr::launch_defect_final(pl->io_ref + (size_t)k * ninst, ninst, s));
+    }
+    if (pl->timed) HIPCHK(hipEventRecord(pl->ev[4 + 3 * k], s));
+    return PR_OK;
+}
+
+int enqueue_head(pr_plan *pl, hipStream_t s)
+{
+    HIPCHK(pr::launch_pointwise(pr::kOpCopy64, pl->dtype, pl->io_u0, pl->ninst, false, s));
+    if (pl->timed) HIPCHK(hipEventRecord(pl->ev[0], s));
+    int rc = enqueue_init(pl, s);
+    if (rc) return rc;
+    if (pl->timed) HIPCHK(hipEventRecord(pl->ev[1], s));
+    return PR_OK;
+}
+
+int enqueue_tail(pr_plan *pl, hipStream_t s)
+{
+    HIPCHK(pr::launch_pointwise(pr::kOpCopy64, pl->dtype, pl->io_uT, pl->ninst, false, s));
+    if (pl->timed) HIPCHK(hipEventRecord(pl->ev.back(), s));
+    return PR_OK;
+}
+
+int enqueue_all(pr_plan *pl, hipStream_t s, bool with_ref)
+{
+    int rc = enqueue_head(pl, s);
+    if (rc) return rc;
+    for (int k = 0; k < pl->K; ++k) {
+        rc = enqueue_iteration(pl, k, s, with_ref);
+        if (rc) return rc;
+    }
+    return enqueue_tail(pl, s);
+}
+
+int count_launches(const pr_plan *pl, double *nf, double *ng)
+{
+    double f = 0, g = 0;
+    for (int k = 0; k < pl->iters_done; ++k) {
+        if (!pl->per_slice) {
+            f += (double)pl->fine_active_blocks[k].size();
+        } else {
+            for (int i = 0; i < pl->ninst; ++i)
+                for (int n = (pl->skip ? k : 0); n < pl->inst[i].P; ++n) f += pl->inst[i].nf;
+        }
+        for (int n = (pl->skip ? k + 1 : 0); n < pl->Pmax; ++n) g += pl->coarse_nch[n];
+    }
+    for (int n = 0; n < pl->Pmax; ++n) g += pl->coarse_nch[n];
+    *nf = f;
+    *ng = g;
+    return PR_OK;
+}
+
+}  // namespace
+
+// ===========================================================================
+// C ABI
+// ===========================================================================
+
+extern "C" {
+
+const char *pr_last_error(void) { return g_err.c_str(); }
+
+const char *pr_version(void) { return "pr 0.1 gfx950"; }
+
+int pr_check_stability(const pr_problem *prob, double *fine_margin, double *coarse_margin)
+{
+    int rc = validate_problem(prob, false);
+    if (rc) return rc;
+    double fm = 0, cm = 0;
+    margins(*prob, &fm, &cm);
+    if (fine_margin) *fine_margin = fm;
+    if (coarse_margin) *coarse_margin = cm;
+    if (fm > 1.0 + 1e-12 || cm > 1.0 + 1e-12)
+        return fail(PR_EUNSTABLE, "unstable: fine margin %.6g, coarse margin %.6g", fm, cm);
+    return PR_OK;
+}
+
+size_t pr_sweep_workspace_bytes(const pr_problem *prob, int32_t dtype, int32_t batch)
+{
+    if (validate_problem(prob, false) || batch < 1 || (dtype != PR_FP32 && dtype != PR_FP64)) return 0;
+    return sweep_ws(*prob, dtype, batch, g_fine_forced == 1);
+}
+
+int pr_fine_sweep(const pr_problem *prob, int32_t dtype, int32_t batch, const void *u_in, void *u_out,
+                  const int64_t *step0, int32_t nsteps, void *ws, size_t ws_bytes, void *stream)
+{
+    return sweep_common(prob, dtype, batch, u_in, u_out, step0, nsteps, ws, ws_bytes, stream, true);
+}
+
+int pr_coarse_sweep(const pr_problem *prob, int32_t dtype, int32_t batch, const void *u_in, void *u_out,
+                    const int64_t *step0, int32_t nsteps, void *ws, size_t ws_bytes, void *stream)
+{
+    return sweep_common(prob, dtype, batch, u_in, u_out, step0, nsteps, ws, ws_bytes, stream, false);
+}
+
+int pr_parareal_update(int64_t npts, int32_t batch, int32_t sweep_dtype, const void *f_new, const void *g_new,
+                       const void *g_old, double *u_out, void *u_out_lo, void *stream)
+{
+    if (npts < 0 || batch < 1) return fail(PR_EINVAL, "npts must be >= 0 and batch >= 1");
+    if (sweep_dtype != PR_FP32 && sweep_dtype != PR_FP64) return fail(PR_EINVAL, "bad sweep dtype");
+    if (!f_new || !g_new || !g_old || !u_out) return fail(PR_EINVAL, "NULL field pointer");
+    if (npts == 0) return PR_OK;
+    int rc = device_ready();
+    if (rc) return rc;
+    PointItem it{};
+    it.a = f_new;
+    it.b = g_new;
+    it.c = g_old;
+    it.u = u_out;
+    it.ulo = u_out_lo;
+    it.npts = npts * batch;
+    HIPCHK(pr::launch_pointwise_inline(pr::kOpCorrect, sweep_dtype, it, (hipStream_t)stream));
+    return PR_OK;
+}
+
+size_t pr_defect_workspace_bytes(int32_t batch)
+{
+    if (batch < 1) return 0;
+    return align256((size_t)batch * sizeof(PointItem)) + (size_t)batch * pr::kNormBlocks * 4 * sizeof(double);
+}
+
+int pr_defect_norm(int64_t npts, int32_t batch, int32_t xd, const void *x, int32_t rd, const void *ref,
+                   double *out4, void *ws, size_t ws_bytes, void *stream)
+{
+    if (npts < 1 || batch < 1) return fail(PR_EINVAL, "npts and batch must be >= 1");
+    if ((xd != PR_FP32 && xd != PR_FP64) || (rd != PR_FP32 && rd != PR_FP64)) return fail(PR_EINVAL, "bad dtype");
+    if (!x || !ref || !out4) return fail(PR_EINVAL, "NULL pointer");
+    const size_t need = pr_defect_workspace_bytes(batch);
+    if (!ws || ws_bytes < need) return fail(PR_ENOMEM, "workspace of %zu bytes < %zu needed", ws_bytes, need);
+    int rc = device_ready();
+    if (rc) return rc;
+    char *w = (char *)ws;
+    PointItem *table = (PointItem *)w;
+    double *part = (double *)(w + align256((size_t)batch * sizeof(PointItem)));
+    std::vector<PointItem> items(batch);
+    for (int b = 0; b < batch; ++b) {
+        PointItem &it = items[b];
+        it = PointItem{};
+        it.a = (const char *)x + (size_t)b * npts * esize(xd);
+        it.b = (const char *)ref + (size_t)b * npts * esize(rd);
+        it.partials = part + (size_t)b * pr::kNormBlocks * 4;
+        it.out4 = out4 + 4 * (size_t)b;
+        it.npts = npts;
+    }
+    hipStream_t s = (hipStream_t)stream;
+    HIPCHK(pr::launch_write_points(items.data(), batch, table, s));
+    HIPCHK(pr::launch_defect_partials(xd, rd, table, batch, s));
+    HIPCHK(pr::launch_defect_final(table, batch, s));
+    return PR_OK;
+}
+
+size_t pr_plan_workspace_bytes(const pr_problem *probs, int32_t ninst, int32_t mode)
+{
+    if (validate_plan_args(probs, ninst, mode)) return 0;
+    return plan_layout(probs, ninst, mode, nullptr, nullptr);
+}
+
+int pr_plan_create(const pr_problem *probs, int32_t ninst, int32_t mode, void *ws, size_t ws_bytes, pr_plan **out)
+{
+    if (!out) return fail(PR_EINVAL, "out is NULL");
+    *out = nullptr;
+    int rc = validate_plan_args(probs, ninst, mode);
+    if (rc) return rc;
+    const size_t need = plan_layout(probs, ninst, mode, nullptr, nullptr);
+    if (!ws || ws_bytes < need) return fail(PR_ENOMEM, "workspace of %zu bytes < %zu needed", ws_bytes, need);
+    rc = device_ready();
+    if (rc) return rc;
+
+    pr_plan *pl = new pr_plan();
+    pl->ninst = ninst;
+    pl->mode = mode;
+    pl->mixed = (mode & PR_MODE_MIXED) != 0;
+    pl->per_slice = (mode & PR_MODE_PER_SLICE) != 0;
+    pl->dtype = pl->mixed ? PR_FP32 : PR_FP64;
+    pl->K = probs[0].K;
+    pl->flags = probs[0].flags;
+    pl->skip = (pl->flags & PR_SKIP_CONVERGED) != 0;
+    pl->early = (pl->flags & PR_EARLY_STOP) != 0;
+    pl->timed = (mode & PR_MODE_TIMED) != 0;
+    pl->graph = (mode & PR_MODE_GRAPH) != 0 && !pl->early && !pl->timed;
+    pl->probs.assign(probs, probs + ninst);
+
+    // one fused variant for all instances: the choice for instance 0 if it
+    // applies to every instance, else the generic one-point-per-thread layout
+    int fv = pick_fine(probs[0], pl->dtype), cv = pick_coarse(probs[0], pl->dtype);
+    bool fok = fv >= 1, cok = cv >= 1;
+    for (int i = 0; i < ninst; ++i) {
+        fok = fok && fine_applicable(fv, pl->dtype, probs[i].fine_order, probs[i]);
+        cok = cok && coarse_applicable(cv, pl->dtype, probs[i]);
+        if (probs[i].fine_order != probs[0].fine_order) {
+            delete pl;
+            return fail(PR_EUNSUPPORTED, "instances of one plan must share fine_order");
+        }
+    }
+    if (!fok) {
+        // fall back to the layout with one x point per thread (any n_x)
+        pr_problem odd = probs[0];
+        odd.n[0] = 3;
+        fv = g_fine_forced ? -1 : pick_fine_default(odd, pl->dtype);
+    }
+    if (!cok) {
+        pr_problem odd = probs[0];
+        odd.n[0] = 3;
+        cv = g_coarse_forced ? -1 : pick_coarse_default(odd, pl->dtype);
+    }
+    if (fv < 1 || cv < 1) {
+        delete pl;
+        return fail(PR_EUNSUPPORTED, "forced kernel variant does not apply to every instance");
+    }
+    pl->fine_v = fv;
+    pl->coarse_v = cv;
+
+    plan_layout(probs, ninst, mode, (char *)ws, pl);
+    rc = build_tables(pl);
+    if (rc) {
+        delete pl;
+        return rc;
+    }
+    if (pl->timed) {
+        pl->ev.resize(3 + 3 * std::max(pl->K, 1));
+        for (auto &e : pl->ev) {
+            hipError_t er = hipEventCreate(&e);
+            if (er != hipSuccess) {
+                pr_plan_destroy(pl);
+                return fail(PR_EDEVICE, "hipEventCreate failed: %s", hipGetErrorString(er));
+            }
+        }
+    }
+    *out = pl;
+    return PR_OK;
+}
+
+void pr_plan_destroy(pr_plan *plan)
+{
+    if (!plan) return;
+    if (plan->exec) (void)hipGraphExecDestroy(plan->exec);
+    if (plan->graph_h) (void)hipGraphDestroy(plan->graph_h);
+    for (auto &e : plan->ev)
+        if (e) (void)hipEventDestroy(e);
+    if (plan->own) (void)hipStreamDestroy(plan->own);
+    delete plan;
+}
+
+int pr_plan_iterations(const pr_plan *plan) { return plan ? plan->iters_done : 0; }
+
+int pr_plan_slice_state(const pr_plan *plan, int32_t inst, int32_t n, const double **out)
+{
+    if (!plan || !out) return fail(PR_EINVAL, "NULL argument");
+    if (inst < 0 || inst >= plan->ninst) return fail(PR_EINVAL, "instance out of range");
+    if (n < 0 || n > plan->inst[inst].P) return fail(PR_EINVAL, "slice boundary out of range");
+    *out = plan->inst[inst].U + (size_t)n * plan->inst[inst].npts;
+    return PR_OK;
+}
+
+int pr_plan_timings(const pr_plan *plan, double *out6)
+{
+    if (!plan || !out6) return fail(PR_EINVAL, "NULL argument");
+    if (!plan->timed) return fail(PR_EINVAL, "plan was not created with PR_MODE_TIMED");
+    for (int i = 0; i < 6; ++i) out6[i] = plan->timings[i];
+    return PR_OK;
+}
+
+int pr_parareal_solve(pr_plan *pl, const double *const *u0, double *const *uT, const double *const *ref, double *log,
+                      void *stream)
+{
+    if (!pl) return fail(PR_EINVAL, "plan is NULL");
+    if (!u0 || !uT) return fail(PR_EINVAL, "u0/uT is NULL");
+    for (int i = 0; i < pl->ninst; ++i) {
+        if (!u0[i] || !uT[i]) return fail(PR_EINVAL, "u0[%d]/uT[%d] is NULL", i, i);
+        if (ref && !ref[i]) return fail(PR_EINVAL, "ref[%d] is NULL", i);
+    }
+    int rc = device_ready();
+    if (rc) return rc;
+    hipStream_t s = (hipStream_t)stream;
+    const int ninst = pl->ninst, K = pl->K;
+    const bool with_ref = ref != nullptr;
+
+    // per-solve I/O tables
+    std::vector<PointItem> io(ninst), ioT(ninst);
+    for (int i = 0; i < ninst; ++i) {
+        const pr_plan::Inst &in = pl->inst[i];
+        io[i] = PointItem{};
+        io[i].a = u0[i];
+        io[i].u = in.U;
+        io[i].ulo = pl->mixed ? (void *)in.Ulo : nullptr;
+        io[i].npts = in.npts;
+        ioT[i] = PointItem{};
+        ioT[i].a = in.U + (size_t)in.P * in.npts;
+        ioT[i].u = uT[i];
+        ioT[i].npts = in.npts;
+    }
+    HIPCHK(pr::launch_write_points(io.data(), ninst, pl->io_u0, s));
+    HIPCHK(pr::launch_write_points(ioT.data(), ninst, pl->io_uT, s));
+    if (with_ref && K > 0) {
+        std::vector<PointItem> ir((size_t)K * ninst);
+        for (int k = 0; k < K; ++k)
+            for (int i = 0; i < ninst; ++i) {
+                const pr_plan::Inst &in = pl->inst[i];
+                PointItem r{};
+                r.a = in.U + (size_t)in.P * in.npts;
+                r.b = ref[i];
+                r.partials = in.refpart;
+                r.out4 = pl->dlog_ref + ((size_t)k * ninst + i) * 4;
+                r.npts = in.npts;
+                ir[(size_t)k * ninst + i] = r;
+            }
+        HIPCHK(pr::launch_write_points(ir.data(), (int)ir.size(), pl->io_ref, s));
+    }
+
+    pl->iters_done = K;
+    if (pl->graph) {
+        if (!pl->exec || pl->had_ref_graph != with_ref) {
+            if (pl->exec) {
+                HIPCHK(hipGraphExecDestroy(pl->exec));
+                pl->exec = nullptr;
+            }
+            if (pl->graph_h) {
+                HIPCHK(hipGraphDestroy(pl->graph_h));
+                pl->graph_h = nullptr;
+            }
+            if (!pl->own) HIPCHK(hipStreamCreateWithFlags(&pl->own, hipStreamNonBlocking));
+            HIPCHK(hipStreamBeginCapture(pl->own, hipStreamCaptureModeThreadLocal));
+            rc = enqueue_all(pl, pl->own, with_ref);
+            hipGraph_t g = nullptr;
+            hipError_t ee = hipStreamEndCapture(pl->own, &g);
+            if (rc) {
+                if (g) (void)hipGraphDestroy(g);
+                return rc;
+            }
+            if (ee != hipSuccess) return fail(PR_EDEVICE, "hipStreamEndCapture failed: %s", hipGetErrorString(ee));
+            pl->graph_h = g;
+            HIPCHK(hipGraphInstantiate(&pl->exec, g, nullptr, nullptr, 0));
+            pl->had_ref_graph = with_ref;
+        }
+        HIPCHK(hipGraphLaunch(pl->exec, s));
+    } else if (pl->early) {
+        rc = enqueue_head(pl, s);
+        if (rc) return rc;
+        pl->iters_done = 0;
+        for (int k = 0; k < K; ++k) {
+            rc = enqueue_iteration(pl, k, s, with_ref);
+            if (rc) return rc;
+            pl->iters_done = k + 1;
+            HIPCHK(hipStreamSynchronize(s));
+            bool all = true;
+            for (int i = 0; i < ninst; ++i) {
+                double e4[4];
+                const int slot = pl->slice_base[i] + pl->inst[i].P - 1;
+                HIPCHK(hipMemcpy(e4, pl->dlog + ((size_t)k * pl->sumP + slot) * 4, sizeof e4, hipMemcpyDeviceToHost));
+                if (!(e4[0] <= pl->probs[0].tol * e4[1])) all = false;
+            }
+            if (all) break;
+        }
+        rc = enqueue_tail(pl, s);
+        if (rc) return rc;
+    } else {
+        rc = enqueue_all(pl, s, with_ref);
+        if (rc) return rc;
+    }
+    HIPCHK(hipStreamSynchronize(s));
+
+    // logs
+    const int Kd = pl->iters_done;
+    std::vector<double> dl((size_t)std::max(K, 1) * pl->sumP * 4, 0.0), dr((size_t)std::max(K, 1) * ninst * 4, 0.0);
+    if (Kd > 0) {
+        HIPCHK(hipMemcpy(dl.data(), pl->dlog, (size_t)Kd * pl->sumP * 4 * sizeof(double), hipMemcpyDeviceToHost));
+        if (with_ref)
+            HIPCHK(hipMemcpy(dr.data(), pl->dlog_ref, (size_t)Kd * ninst * 4 * sizeof(double), hipMemcpyDeviceToHost));
+    }
+    bool finite = true;
+    for (int i = 0; i < ninst; ++i) {
+        const int P = pl->inst[i].P;
+        for (int k = 0; k < Kd; ++k) {
+            double row[12] = {0};
+            const double *fin = &dl[((size_t)k * pl->sumP + pl->slice_base[i] + P - 1) * 4];
+            for (int c = 0; c < 4; ++c) row[c] = fin[c];
+            for (int n = 0; n < P; ++n) {
+                const bool computed = !pl->skip || n >= k;
+                const int kk = computed ? k : n;  // slice n last changed in iteration n
+                const double *e = &dl[((size_t)kk * pl->sumP + pl->slice_base[i] + n) * 4];
+                const double dmax = computed ? e[0] : 0.0, dsum = computed ? e[2] : 0.0;
+                row[4] = std::max(row[4], dmax);
+                row[5] = std::max(row[5], e[1]);
+                row[6] += dsum;
+                row[7] += e[3];
+            }
+            if (with_ref)
+                for (int c = 0; c < 4; ++c) row[8 + c] = dr[((size_t)k * ninst + i) * 4 + c];
+            for (int c : {2, 3, 6, 7, 10, 11})
+                if (!std::isfinite(row[c])) finite = false;
+            if (log)
+                for (int c = 0; c < 12; ++c) log[((size_t)i * K + k) * 12 + c] = row[c];
+        }
+    }
+    if (pl->timed) {
+        float ms = 0;
+        double f = 0, g = 0;
+        HIPCHK(hipEventElapsedTime(&ms, pl->ev[0], pl->ev[1]));
+        pl->timings[2] = ms;
+        for (int k = 0; k < Kd; ++k) {
+            HIPCHK(hipEventElapsedTime(&ms, pl->ev[2 + 3 * k], pl->ev[3 + 3 * k]));
+            f += ms;
+            HIPCHK(hipEventElapsedTime(&ms, pl->ev[3 + 3 * k], pl->ev[4 + 3 * k]));
+            g += ms;
+        }
+        pl->timings[0] = f;
+        pl->timings[1] = g;
+        double nf = 0, ng = 0;
+        count_launches(pl, &nf, &ng);
+        pl->timings[3] = nf;
+        pl->timings[4] = ng;
+        HIPCHK(hipEventElapsedTime(&ms, pl->ev[0], pl->ev.back()));
+        pl->timings[5] = ms;
+    }
+    if (!finite) return fail(PR_ENONFINITE, "a defect norm is not finite (the iteration diverged or the input holds NaN/Inf)");
+    return PR_OK;
+}
+
+int pr_set_kernel_variant(int32_t fine_variant, int32_t coarse_variant)
+{
+    if (fine_variant < 0 || fine_variant >= pr::fine_variant_count()) return fail(PR_EINVAL, "fine variant out of range");
+    if (coarse_variant < 0 || coarse_variant >= pr::coarse_variant_count())
+        return fail(PR_EINVAL, "coarse variant out of range");
+    g_fine_forced = fine_variant;
+    g_coarse_forced = coarse_variant;
+    return PR_OK;
+}
+
+int pr_kernel_variant_count(int32_t which) { return which == 0 ? pr::fine_variant_count() : pr::coarse_variant_count(); }
+
+const char *pr_kernel_variant_name(int32_t which, int32_t variant)
+{
+    if (variant == 0) return "auto";
+    if (variant == 1) return which == 0 ? "rk4_unfused_reference" : "euler_unfused_reference";
+    const VariantInfo *vi = which == 0 ? pr::fine_variant(variant) : pr::coarse_variant(variant);
+    return vi ? vi->name : "invalid";
+}
+
+int pr_kernel_variant_info(int32_t which, int32_t variant, int32_t *dtype, int32_t *order, int32_t *tile_x,
+                           int32_t *tile_y, int32_t *nxp, int32_t *steps)
+{
+    const VariantInfo *vi = which == 0 ? pr::fine_variant(variant) : pr::coarse_variant(variant);
+    if (!vi) return fail(PR_EINVAL, "no fused variant %d", variant);
+    if (dtype) *dtype = vi->dtype;
+    if (order) *order = vi->order;
+    if (tile_x) *tile_x = vi->tx;
+    if (tile_y) *tile_y = vi->ty;
+    if (nxp) *nxp = vi->nxp;
+    if (steps) *steps = vi->steps;
+    return PR_OK;
+}
+
+size_t pr_autotune_workspace_bytes(const pr_problem *prob, int32_t dtype, int32_t batch)
+{
+    if (validate_problem(prob, false) || batch < 1 || (dtype != PR_FP32 && dtype != PR_FP64)) return 0;
+    const size_t states = (size_t)batch * npts_of(*prob) * esize(dtype);
+    return 2 * align256(states) + sweep_ws(*prob, dtype, batch, false);
+}
+
+int pr_autotune(const pr_problem *prob, int32_t dtype, int32_t batch, int32_t which, void *ws, size_t ws_bytes,
+                void *stream, int32_t *best_variant)
+{
+    int rc = validate_problem(prob, false);
+    if (rc) return rc;
+    if (which != 0 && which != 1) return fail(PR_EINVAL, "which must be 0 (fine) or 1 (coarse)");
+    const size_t need = pr_autotune_workspace_bytes(prob, dtype, batch);
+    if (!need) return fail(PR_EINVAL, "bad dtype or batch");
+    if (!ws || ws_bytes < need) return fail(PR_ENOMEM, "workspace of %zu bytes < %zu needed", ws_bytes, need);
+    rc = device_ready();
+    if (rc) return rc;
+    hipStream_t s = (hipStream_t)stream;
+    const size_t states = (size_t)batch * npts_of(*prob) * esize(dtype);
+    char *a = (char *)ws, *b = a + align256(states), *w = b + align256(states);
+    const size_t wsb = sweep_ws(*prob, dtype, batch, false);
+    HIPCHK(hipMemsetAsync(a, 0, states, s));
+    pr_problem p = *prob;
+    p.flags |= PR_ALLOW_UNSTABLE;  // zeros stay zeros; timing only
+    std::vector<int64_t> st(batch, 0);
+    const int saved_f = g_fine_forced, saved_c = g_coarse_forced;
+    hipEvent_t e0, e1;
+    HIPCHK(hipEventCreate(&e0));
+    HIPCHK(hipEventCreate(&e1));
+    float best = 1e30f;
+    int bestv = -1;
+    const int nv = which == 0 ? pr::fine_variant_count() : pr::coarse_variant_count();
+    for (int v = 2; v < nv; ++v) {
+        const bool ok = which == 0 ? fine_applicable(v, dtype, p.fine_order, p) : coarse_applicable(v, dtype, p);
+        if (!ok) continue;
+        if (which == 0) g_fine_forced = v;
+        else g_coarse_forced = v;
+        const int steps = which == 0 ? 6 : 8 * coarse_steps_per_launch(v);
+        rc = sweep_common(&p, dtype, batch, a, b, st.data(), which == 0 ? 2 : 2 * coarse_steps_per_launch(v), w, wsb, s,
+                          which == 0);
+        if (rc) break;
+        (void)hipEventRecord(e0, s);
+        rc = sweep_common(&p, dtype, batch, a, b, st.data(), steps, w, wsb, s, which == 0);
+        (void)hipEventRecord(e1, s);
+        if (rc) break;
+        (void)hipEventSynchronize(e1);
+        float ms = 0;
+        (void)hipEventElapsedTime(&ms, e0, e1);
+        const float per = ms / steps;
+        if (per < best) {
+            best = per;
+            bestv = v;
+        }
+    }
+    g_fine_forced = saved_f;
+    g_coarse_forced = saved_c;
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (rc) return rc;
+    if (bestv < 0) return fail(PR_EUNSUPPORTED, "no fused variant applies");
+    {
+        std::lock_guard<std::mutex> lk(g_tune_mu);
+        g_tuned[{which, p.n[0], p.n[1], p.n[2], dtype, which == 0 ? p.fine_order : 0}] = bestv;
+    }
+    if (best_variant) *best_variant = bestv;
+    return PR_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,760 @@
+// Stencil kernels of the fine propagator F (classical RK4, centered stencils)
+// and the coarse propagator G (forward Euler, upwind advection) for gfx950.
+//
+// Fused kernels march along z.  A block owns an x-y tile extended by a halo
+// of (stages x stencil radius) points in x and y, and walks the whole z range
+// of its chunk plane by plane.  Every stage of the step (four RK4 stages, or
+// S Euler steps) is evaluated on the fly, lagging its predecessor by one
+// stencil radius in z: stage inputs live in per-thread register rings of z
+// planes, and the current plane of each stage input is exchanged through
+// LDS for the in-plane neighbours.  One step therefore costs one read and one
+// write of the field in HBM; the halo is recomputed redundantly.
+//
+// Per-point arithmetic is fixed by `apply()` (operand order and explicit
+// fused multiply-adds) and shared with the unfused reference kernels, so
+// every kernel variant, tile shape and launch order yields bitwise identical
+// fields.
+#include "pr_internal.h"
+
+#include <utility>
+
+namespace pr {
+namespace {
+
+template <int N>
+using ic = std::integral_constant<int, N>;
+
+template <typename T, int N>
+struct alignas(sizeof(T) * N) Vec {
+    T v[N];
+};
+
+__device__ __forceinline__ int wrapi(int i, int n)
+{
+    int r = i % n;
+    return r < 0 ? r + n : r;
+}
+
+// Blocks are dispatched round-robin over the 8 XCDs.  Give each XCD a
+// contiguous range of logical blocks so that neighbouring tiles (which read
+// each other's halos) share an L2.
+__device__ __forceinline__ int xcd_remap(int b, int n)
+{
+    const int q = n >> 3, r = n & 7;
+    const int x = b & 7, k = b >> 3;
+    return x * q + (x < r ? x : r) + k;
+}
+
+__device__ __forceinline__ int find_item(const ItemDesc *__restrict__ items, int nitems, int lb)
+{
+    int lo = 0, hi = nitems - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (items[mid].block_begin <= lb) lo = mid;
+        else hi = mid - 1;
+    }
+    return lo;
+}
+
+__device__ __forceinline__ double nu_at(const ItemDesc &it, double t)
+{
+    return it.nu0 * (1.0 + it.nu_amp * sin(it.nu_omega * t));
+}
+
+__device__ __forceinline__ float fmaT(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
+__device__ __forceinline__ double fmaT(double a, double b, double c) { return __builtin_fma(a, b, c); }
+
+// Stencil weights of one stage: centre, and for every axis d the weights of
+// the points at -k and +k (k = 1..R).
+template <typename T, int R>
+struct Wts {
+    T c;
+    T m[3][R];
+    T p[3][R];
+};
+
+// Fine operator L = nu Lap - a.grad, centered differences of order 2R.
+template <typename T, int R>
+__device__ __forceinline__ Wts<T, R> fine_weights(const ItemDesc &it, double nu)
+{
+    Wts<T, R> w;
+    double c = 0.0;
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+        const double dif = nu * it.inv_h2[d];
+        const double adv = it.a_over_h[d];
+        if constexpr (R == 1) {
+            w.m[d][0] = (T)(dif + 0.5 * adv);
+            w.p[d][0] = (T)(dif - 0.5 * adv);
+            c += -2.0 * dif;
+        } else {
+            w.m[d][0] = (T)(dif * (16.0 / 12.0) + adv * (8.0 / 12.0));
+            w.p[d][0] = (T)(dif * (16.0 / 12.0) - adv * (8.0 / 12.0));
+            w.m[d][1] = (T)(-dif * (1.0 / 12.0) - adv * (1.0 / 12.0));
+            w.p[d][1] = (T)(-dif * (1.0 / 12.0) + adv * (1.0 / 12.0));
+            c += -dif * (30.0 / 12.0);
+        }
+    }
+    w.c = (T)c;
+    return w;
+}
+
+// Coarse operator of Algorithm 2: nu * 7-point Laplacian, minus first-order
+// upwind advection (backward difference for a_d > 0, forward otherwise).
+template <typename T>
+__device__ __forceinline__ Wts<T, 1> coarse_weights(const ItemDesc &it, double nu)
+{
+    Wts<T, 1> w;
+    double c = 0.0;
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+        const double dif = nu * it.inv_h2[d];
+        const double adv = it.a_over_h[d];
+        double m = dif, p = dif;
+        c += -2.0 * dif;
+        if (adv > 0.0) {
+            c -= adv;
+            m += adv;
+        } else {
+            c += adv;
+            p -= adv;
+        }
+        w.m[d][0] = (T)m;
+        w.p[d][0] = (T)p;
+    }
+    w.c = (T)c;
+    return w;
+}
+
+// The one definition of a stencil application: centre product, then per axis
+// x, y, z and per distance k the -k and +k neighbours, each a fused
+// multiply-add.  Every kernel evaluates S through this function.
+template <typename T, int R>
+__device__ __forceinline__ T apply(const Wts<T, R> &w, T cen, const T (&mn)[3][R], const T (&pn)[3][R])
+{
+    T s = w.c * cen;
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+#pragma unroll
+        for (int k = 0; k < R; ++k) {
+            s = fmaT(w.m[d][k], mn[d][k], s);
+            s = fmaT(w.p[d][k], pn[d][k], s);
+        }
+    }
+    return s;
+}
+
+template <typename T>
+struct RK4Consts {
+    T c1, c2, c3, b1, b2, b3, b4;
+};
+
+template <typename T>
+__device__ __forceinline__ RK4Consts<T> rk4_consts(double dt)
+{
+    RK4Consts<T> k;
+    k.c1 = (T)(0.5 * dt);
+    k.c2 = (T)(0.5 * dt);
+    k.c3 = (T)dt;
+    k.b1 = (T)(dt / 6.0);
+    k.b2 = (T)(dt / 3.0);
+    k.b3 = (T)(dt / 3.0);
+    k.b4 = (T)(dt / 6.0);
+    return k;
+}
+
+// Step j reads the field written by step j-1 and writes dst for the last step.
+template <typename T>
+__device__ __forceinline__ void pingpong(const ItemDesc &it, int j, int n, const T *&src, T *&dst)
+{
+    src = (j == 0) ? (const T *)it.src0 : ((((n - j) & 1) == 0) ? (const T *)it.dst : (const T *)it.tmp);
+    dst = ((((n - 1 - j) & 1) == 0) ? (T *)it.dst : (T *)it.tmp);
+}
+
+template <int L>
+__host__ __device__ constexpr int slot(int m, int off)
+{
+    return ((m - off) % L + L) % L;
+}
+
+// ---------------------------------------------------------------------------
+// Fused RK4 step.  Tile of EX x EY threads-points (BXT x BY threads, each
+// owning NXP consecutive x and NY consecutive y), output TX x TY, halo 4R.
+// ---------------------------------------------------------------------------
+template <typename T, int R, int NXP, int NY, int BXT, int BY>
+__global__ void __launch_bounds__(BXT *BY)
+    rk4_step_fused(const ItemDesc *__restrict__ items, int nitems, int jstep)
+{
+    constexpr int H = 4 * R;
+    constexpr int EX = BXT * NXP, EY = BY * NY;
+    constexpr int TX = EX - 2 * H, TY = EY - 2 * H;
+    constexpr int L = 3 * R + 1;                       // z-ring length
+    constexpr int CO = ((R + NXP - 1) / NXP) * NXP;    // LDS column offset (aligned halo)
+    constexpr int LX = EX + 2 * CO + (sizeof(T) == 8 ? 2 : 4);
+    constexpr int LY = EY + 2 * R;
+    static_assert(TX > 0 && TY > 0, "tile too small for the halo");
+    __shared__ __align__(16) T lds[2][LY][LX];
+
+    const int lb = xcd_remap((int)blockIdx.x, (int)gridDim.x);
+    const ItemDesc &it = items[find_item(items, nitems, lb)];
+    if (jstep >= it.nsteps) return;
+    const int local = lb - it.block_begin;
+    if (local < 0 || local >= it.nblocks) return;
+
+    const int nx = it.nx, ny = it.ny, nz = it.nz;
+    const int txt = local % it.tiles_x;
+    const int rest = local / it.tiles_x;
+    const int tyt = rest % it.tiles_y;
+    const int zc = rest / it.tiles_y;
+    const int x0 = txt * TX, y0 = tyt * TY;
+    const int z0 = zc * it.tz;
+    const int zend = min(z0 + it.tz, nz);
+
+    const T *src;
+    T *dst;
+    pingpong<T>(it, jstep, it.nsteps, src, dst);
+
+    const int tid = (int)threadIdx.x;
+    const int txi = tid % BXT, tyi = tid / BXT;
+    const int cx0 = txi * NXP, ry0 = tyi * NY;
+    const int gx0 = wrapi(x0 - H + cx0, nx);
+    int rowoff[NY];
+    bool yok[NY];
+#pragma unroll
+    for (int iy = 0; iy < NY; ++iy) {
+        const int ry = ry0 + iy;
+        rowoff[iy] = wrapi(y0 - H + ry, ny) * nx + gx0;
+        yok[iy] = (ry >= H) && (ry < H + TY) && (y0 + ry - H < ny);
+    }
+    const bool xok = (cx0 >= H) && (cx0 < H + TX) && (x0 + cx0 - H < nx);
+    const int nxy = nx * ny;
+
+    // stage times and weights
+    const double dt = it.dt;
+    const double t = (double)(it.step0 + jstep) * dt;
+    const double nu1 = nu_at(it, t);
+    const double nu2 = it.frozen ? nu1 : nu_at(it, t + 0.5 * dt);
+    const double nu4 = it.frozen ? nu1 : nu_at(it, t + dt);
+    const Wts<T, R> w1 = fine_weights<T, R>(it, nu1);
+    const Wts<T, R> w2 = fine_weights<T, R>(it, nu2);
+    const Wts<T, R> w4 = fine_weights<T, R>(it, nu4);
+    const RK4Consts<T> kc = rk4_consts<T>(dt);
+
+    T ur[L][NY][NXP], y1[L][NY][NXP], y2[L][NY][NXP], y3[L][NY][NXP], ac[L][NY][NXP];
+    T pf[NY][NXP];
+
+    auto load_plane = [&](int p) {
+        const T *base = src + (size_t)wrapi(p, nz) * nxy;
+#pragma unroll
+        for (int iy = 0; iy < NY; ++iy) {
+            const Vec<T, NXP> v = *reinterpret_cast<const Vec<T, NXP> *>(base + rowoff[iy]);
+#pragma unroll
+            for (int ix = 0; ix < NXP; ++ix) pf[iy][ix] = v.v[ix];
+        }
+    };
+
+    // Evaluate S = L(f)(plane at offset OFF from p) for the thread's points,
+    // f given by its z-ring `in`; uses LDS buffer BUF.
+    auto stage = [&](auto Mc, auto OFFc, auto BUFc, T(&in)[L][NY][NXP], const Wts<T, R> &w, bool active,
+                     T(&S)[NY][NXP]) {
+        constexpr int M = decltype(Mc)::value;
+        constexpr int OFF = decltype(OFFc)::value;
+        constexpr int B = decltype(BUFc)::value;
+        constexpr int sc = slot<L>(M, OFF);
+        if (active) {
+#pragma unroll
+            for (int iy = 0; iy < NY; ++iy) {
+                Vec<T, NXP> v;
+#pragma unroll
+                for (int ix = 0; ix < NXP; ++ix) v.v[ix] = in[sc][iy][ix];
+                *reinterpret_cast<Vec<T, NXP> *>(&lds[B][R + ry0 + iy][CO + cx0]) = v;
+            }
+        }
+        __syncthreads();
+        if (active) {
+#pragma unroll
+            for (int iy = 0; iy < NY; ++iy) {
+#pragma unroll
+                for (int ix = 0; ix < NXP; ++ix) {
+                    T mn[3][R], pn[3][R];
+#pragma unroll
+                    for (int k = 1; k <= R; ++k) {
+                        mn[0][k - 1] = (ix - k >= 0) ? in[sc][iy][ix - k] : lds[B][R + ry0 + iy][CO + cx0 + ix - k];
+                        pn[0][k - 1] = (ix + k < NXP) ? in[sc][iy][ix + k] : lds[B][R + ry0 + iy][CO + cx0 + ix + k];
+                        mn[1][k - 1] = (iy - k >= 0) ? in[sc][iy - k][ix] : lds[B][R + ry0 + iy - k][CO + cx0 + ix];
+                        pn[1][k - 1] = (iy + k < NY) ? in[sc][iy + k][ix] : lds[B][R + ry0 + iy + k][CO + cx0 + ix];
+                        mn[2][k - 1] = in[slot<L>(M, OFF + k)][iy][ix];   // plane q - k
+                        pn[2][k - 1] = in[slot<L>(M, OFF - k)][iy][ix];   // plane q + k
+                    }
+                    S[iy][ix] = apply<T, R>(w, in[sc][iy][ix], mn, pn);
+                }
+            }
+        }
+    };
+
+    auto body = [&](auto Mc, int p) {
+        constexpr int M = decltype(Mc)::value;
+#pragma unroll
+        for (int iy = 0; iy < NY; ++iy)
+#pragma unroll
+            for (int ix = 0; ix < NXP; ++ix) ur[slot<L>(M, 0)][iy][ix] = pf[iy][ix];
+        load_plane(p + 1);
+
+        T S[NY][NXP];
+        // stage 1 at plane p - R
+        const bool a1 = p >= z0 - 2 * R;
+        stage(Mc, ic<R>{}, ic<0>{}, ur, w1, a1, S);
+        if (a1) {
+#pragma unroll
+            for (int iy = 0; iy < NY; ++iy)
+#pragma unroll
+                for (int ix = 0; ix < NXP; ++ix) {
+                    const T u = ur[slot<L>(M, R)][iy][ix];
+                    y1[slot<L>(M, R)][iy][ix] = fmaT(kc.c1, S[iy][ix], u);
+                    ac[slot<L>(M, R)][iy][ix] = fmaT(kc.b1, S[iy][ix], u);
+                }
+        }
+        // stage 2 at plane p - 2R
+        const bool a2 = p >= z0;
+        stage(Mc, ic<2 * R>{}, ic<1>{}, y1, w2, a2, S);
+        if (a2) {
+#pragma unroll
+            for (int iy = 0; iy < NY; ++iy)
+#pragma unroll
+                for (int ix = 0; ix < NXP; ++ix) {
+                    const T u = ur[slot<L>(M, 2 * R)][iy][ix];
+                    y2[slot<L>(M, 2 * R)][iy][ix] = fmaT(kc.c2, S[iy][ix], u);
+                    ac[slot<L>(M, 2 * R)][iy][ix] = fmaT(kc.b2, S[iy][ix], ac[slot<L>(M, 2 * R)][iy][ix]);
+                }
+        }
+        // stage 3 at plane p - 3R
+        const bool a3 = p >= z0 + 2 * R;
+        stage(Mc, ic<3 * R>{}, ic<0>{}, y2, w2, a3, S);
+        if (a3) {
+#pragma unroll
+            for (int iy = 0; iy < NY; ++iy)
+#pragma unroll
+                for (int ix = 0; ix < NXP; ++ix) {
+                    const T u = ur[slot<L>(M, 3 * R)][iy][ix];
+                    y3[slot<L>(M, 3 * R)][iy][ix] = fmaT(kc.c3, S[iy][ix], u);
+                    ac[slot<L>(M, 3 * R)][iy][ix] = fmaT(kc.b3, S[iy][ix], ac[slot<L>(M, 3 * R)][iy][ix]);
+                }
+        }
+        // stage 4 at plane p - 4R, result stored
+        const bool a4 = p >= z0 + 4 * R;
+        stage(Mc, ic<4 * R>{}, ic<1>{}, y3, w4, a4, S);
+        const int q = p - 4 * R;
+        if (a4 && q < zend && xok) {
+            T *obase = dst + (size_t)q * nxy;
+#pragma unroll
+            for (int iy = 0; iy < NY; ++iy) {
+                if (yok[iy]) {
+                    Vec<T, NXP> v;
+#pragma unroll
+                    for (int ix = 0; ix < NXP; ++ix)
+                        v.v[ix] = fmaT(kc.b4, S[iy][ix], ac[slot<L>(M, 4 * R)][iy][ix]);
+                    *reinterpret_cast<Vec<T, NXP> *>(obase + rowoff[iy]) = v;
+                }
+            }
+        }
+    };
+
+    const int pstart = z0 - 4 * R;
+    const int niter = (zend - z0) + 8 * R;
+    load_plane(pstart);
+    for (int pb = 0; pb < niter; pb += L) {
+        [&]<int... Ms>(std::integer_sequence<int, Ms...>) {
+            (body(ic<Ms>{}, pstart + pb + Ms), ...);
+        }(std::make_integer_sequence<int, L>{});
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Fused forward Euler chunk: S steps of Algorithm 2 per HBM pass.  Steps past
+// the end of a field's sweep are exact identities (zero step size).
+// ---------------------------------------------------------------------------
+template <typename T, int S, int NXP, int NY, int BXT, int BY>
+__global__ void __launch_bounds__(BXT *BY)
+    euler_chunk_fused(const ItemDesc *__restrict__ items, int nitems, int chunk)
+{
+    constexpr int R = 1;
+    constexpr int H = S;
+    constexpr int EX = BXT * NXP, EY = BY * NY;
+    constexpr int TX = EX - 2 * H, TY = EY - 2 * H;
+    constexpr int L = 3;
+    constexpr int CO = ((R + NXP - 1) / NXP) * NXP;
+    constexpr int LX = EX + 2 * CO + (sizeof(T) == 8 ? 2 : 4);
+    constexpr int LY = EY + 2 * R;
+    static_assert(TX > 0 && TY > 0, "tile too small for the halo");
+    __shared__ __align__(16) T lds[2][LY][LX];
+
+    const int lb = xcd_remap((int)blockIdx.x, (int)gridDim.x);
+    const ItemDesc &it = items[find_item(items, nitems, lb)];
+    const int nchunks = (it.nsteps + S - 1) / S;
+    if (chunk >= nchunks) return;
+    const int local = lb - it.block_begin;
+    if (local < 0 || local >= it.nblocks) return;
+
+    const int nx = it.nx, ny = it.ny, nz = it.nz;
+    const int txt = local % it.tiles_x;
+    const int rest = local / it.tiles_x;
+    const int tyt = rest % it.tiles_y;
+    const int zc = rest / it.tiles_y;
+    const int x0 = txt * TX, y0 = tyt * TY;
+    const int z0 = zc * it.tz;
+    const int zend = min(z0 + it.tz, nz);
+
+    const T *src;
+    T *dst;
+    pingpong<T>(it, chunk, nchunks, src, dst);
+
+    const int tid = (int)threadIdx.x;
+    const int txi = tid % BXT, tyi = tid / BXT;
+    const int cx0 = txi * NXP, ry0 = tyi * NY;
+    const int gx0 = wrapi(x0 - H + cx0, nx);
+    int rowoff[NY];
+    bool yok[NY];
+#pragma unroll
+    for (int iy = 0; iy < NY; ++iy) {
+        const int ry = ry0 + iy;
+        rowoff[iy] = wrapi(y0 - H + ry, ny) * nx + gx0;
+        yok[iy] = (ry >= H) && (ry < H + TY) && (y0 + ry - H < ny);
+    }
+    const bool xok = (cx0 >= H) && (cx0 < H + TX) && (x0 + cx0 - H < nx);
+    const int nxy = nx * ny;
+
+    Wts<T, 1> w[S];
+    T dts[S];
+#pragma unroll
+    for (int s = 0; s < S; ++s) {
+        const int64_t j = (int64_t)chunk * S + s;
+        const bool act = j < it.nsteps;
+        const double nu = nu_at(it, (double)(it.step0 + j) * it.dt);
+        w[s] = coarse_weights<T>(it, nu);
+        dts[s] = act ? (T)it.dt : (T)0;
+    }
+
+    T f[S][L][NY][NXP];
+    T pf[NY][NXP];
+
+    auto load_plane = [&](int p) {
+        const T *base = src + (size_t)wrapi(p, nz) * nxy;
+#pragma unroll
+        for (int iy = 0; iy < NY; ++iy) {
+            const Vec<T, NXP> v = *reinterpret_cast<const Vec<T, NXP> *>(base + rowoff[iy]);
+#pragma unroll
+            for (int ix = 0; ix < NXP; ++ix) pf[iy][ix] = v.v[ix];
+        }
+    };
+
+    auto body = [&](auto Mc, int p) {
+        constexpr int M = decltype(Mc)::value;
+#pragma unroll
+        for (int iy = 0; iy < NY; ++iy)
+#pragma unroll
+            for (int ix = 0; ix < NXP; ++ix) f[0][slot<L>(M, 0)][iy][ix] = pf[iy][ix];
+        load_plane(p + 1);
+
+        [&]<int... Ss>(std::integer_sequence<int, Ss...>) {
+            (
+                [&] {
+                    constexpr int s = Ss + 1;          // stage s computes plane p - s from f[s-1]
+                    constexpr int sc = slot<L>(M, s);
+                    constexpr int B = s & 1;
+                    const bool active = p >= z0 - S + 2 * s;
+                    if (active) {
+#pragma unroll
+                        for (int iy = 0; iy < NY; ++iy) {
+                            Vec<T, NXP> v;
+#pragma unroll
+                            for (int ix = 0; ix < NXP; ++ix) v.v[ix] = f[s - 1][sc][iy][ix];
+                            *reinterpret_cast<Vec<T, NXP> *>(&lds[B][R + ry0 + iy][CO + cx0]) = v;
+                        }
+                    }
+                    __syncthreads();
+                    if (active) {
+                        T res[NY][NXP];
+#pragma unroll
+                        for (int iy = 0; iy < NY; ++iy) {
+#pragma unroll
+                            for (int ix = 0; ix < NXP; ++ix) {
+                                T mn[3][1], pn[3][1];
+                                mn[0][0] = (ix >= 1) ? f[s - 1][sc][iy][ix - 1] : lds[B][R + ry0 + iy][CO + cx0 + ix - 1];
+                                pn[0][0] = (ix + 1 < NXP) ? f[s - 1][sc][iy][ix + 1] : lds[B][R + ry0 + iy][CO + cx0 + ix + 1];
+                                mn[1][0] = (iy >= 1) ? f[s - 1][sc][iy - 1][ix] : lds[B][R + ry0 + iy - 1][CO + cx0 + ix];
+                                pn[1][0] = (iy + 1 < NY) ? f[s - 1][sc][iy + 1][ix] : lds[B][R + ry0 + iy + 1][CO + cx0 + ix];
+                                mn[2][0] = f[s - 1][slot<L>(M, s + 1)][iy][ix];
+                                pn[2][0] = f[s - 1][slot<L>(M, s - 1)][iy][ix];
+                                const T cen = f[s - 1][sc][iy][ix];
+                                const T Sv = apply<T, 1>(w[s - 1], cen, mn, pn);
+                                res[iy][ix] = fmaT(dts[s - 1], Sv, cen);
+                            }
+                        }
+                        if constexpr (s < S) {
+#pragma unroll
+                            for (int iy = 0; iy < NY; ++iy)
+#pragma unroll
+                                for (int ix = 0; ix < NXP; ++ix) f[s][slot<L>(M, s)][iy][ix] = res[iy][ix];
+                        } else {
+                            const int q = p - S;
+                            if (q < zend && xok) {
+                                T *obase = dst + (size_t)q * nxy;
+#pragma unroll
+                                for (int iy = 0; iy < NY; ++iy) {
+                                    if (yok[iy]) {
+                                        Vec<T, NXP> v;
+#pragma unroll
+                                        for (int ix = 0; ix < NXP; ++ix) v.v[ix] = res[iy][ix];
+                                        *reinterpret_cast<Vec<T, NXP> *>(obase + rowoff[iy]) = v;
+                                    }
+                                }
+                            }
+                        }
+                    }
+                }(),
+                ...);
+        }(std::make_integer_sequence<int, S>{});
+    };
+
+    const int pstart = z0 - S;
+    const int niter = (zend - z0) + 2 * S;
+    load_plane(pstart);
+    for (int pb = 0; pb < niter; pb += L) {
+        [&]<int... Ms>(std::integer_sequence<int, Ms...>) {
+            (body(ic<Ms>{}, pstart + pb + Ms), ...);
+        }(std::make_integer_sequence<int, L>{});
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Unfused reference kernels: one thread per point, neighbours read from
+// global memory.  RK4 runs as four stage launches through three scratch
+// fields [Ya | Yb | Acc]; Euler as one launch per step.
+// ---------------------------------------------------------------------------
+template <typename T, int R>
+__device__ __forceinline__ void gather(const T *f, int x, int y, int z, int nx, int ny, int nz, T &cen,
+                                       T (&mn)[3][R], T (&pn)[3][R])
+{
+    const int nxy = nx * ny;
+    cen = f[(size_t)z * nxy + y * nx + x];
+#pragma unroll
+    for (int k = 1; k <= R; ++k) {
+        mn[0][k - 1] = f[(size_t)z * nxy + y * nx + wrapi(x - k, nx)];
+        pn[0][k - 1] = f[(size_t)z * nxy + y * nx + wrapi(x + k, nx)];
+        mn[1][k - 1] = f[(size_t)z * nxy + wrapi(y - k, ny) * nx + x];
+        pn[1][k - 1] = f[(size_t)z * nxy + wrapi(y + k, ny) * nx + x];
+        mn[2][k - 1] = f[(size_t)wrapi(z - k, nz) * nxy + y * nx + x];
+        pn[2][k - 1] = f[(size_t)wrapi(z + k, nz) * nxy + y * nx + x];
+    }
+}
+
+constexpr int kRefThreads = 256;
+
+template <typename T, int R>
+__global__ void __launch_bounds__(kRefThreads)
+    rk4_stage_ref(const ItemDesc *__restrict__ items, int nitems, int jstep, int stagei)
+{
+    const int lb = (int)blockIdx.x;
+    const ItemDesc &it = items[find_item(items, nitems, lb)];
+    if (jstep >= it.nsteps) return;
+    const int local = lb - it.block_begin;
+    const int nx = it.nx, ny = it.ny, nz = it.nz;
+    const int64_t npts = (int64_t)nx * ny * nz;
+    const int64_t idx = (int64_t)local * kRefThreads + threadIdx.x;
+    if (idx >= npts) return;
+    const int x = (int)(idx % nx), y = (int)((idx / nx) % ny), z = (int)(idx / ((int64_t)nx * ny));
+
+    const T *src;
+    T *dst;
+    pingpong<T>(it, jstep, it.nsteps, src, dst);
+    T *Ya = (T *)it.scratch;
+    T *Yb = Ya + npts;
+    T *Ac = Yb + npts;
+
+    const double dt = it.dt;
+    const double t = (double)(it.step0 + jstep) * dt;
+    const double nu1 = nu_at(it, t);
+    const double nu2 = it.frozen ? nu1 : nu_at(it, t + 0.5 * dt);
+    const double nu4 = it.frozen ? nu1 : nu_at(it, t + dt);
+    const RK4Consts<T> kc = rk4_consts<T>(dt);
+
+    T cen, mn[3][R], pn[3][R];
+    if (stagei == 1) {
+        const Wts<T, R> w = fine_weights<T, R>(it, nu1);
+        gather<T, R>(src, x, y, z, nx, ny, nz, cen, mn, pn);
+        const T S = apply<T, R>(w, cen, mn, pn);
+        Ya[idx] = fmaT(kc.c1, S, cen);
+        Ac[idx] = fmaT(kc.b1, S, cen);
+    } else if (stagei == 2) {
+        const Wts<T, R> w = fine_weights<T, R>(it, nu2);
+        gather<T, R>(Ya, x, y, z, nx, ny, nz, cen, mn, pn);
+        const T S = apply<T, R>(w, cen, mn, pn);
+        Yb[idx] = fmaT(kc.c2, S, src[idx]);
+        Ac[idx] = fmaT(kc.b2, S, Ac[idx]);
+    } else if (stagei == 3) {
+        const Wts<T, R> w = fine_weights<T, R>(it, nu2);
+        gather<T, R>(Yb, x, y, z, nx, ny, nz, cen, mn, pn);
+        const T S = apply<T, R>(w, cen, mn, pn);
+        Ya[idx] = fmaT(kc.c3, S, src[idx]);
+        Ac[idx] = fmaT(kc.b3, S, Ac[idx]);
+    } else {
+        const Wts<T, R> w = fine_weights<T, R>(it, nu4);
+        gather<T, R>(Ya, x, y, z, nx, ny, nz, cen, mn, pn);
+        const T S = apply<T, R>(w, cen, mn, pn);
+        dst[idx] = fmaT(kc.b4, S, Ac[idx]);
+    }
+}
+
+template <typename T>
+__global__ void __launch_bounds__(kRefThreads)
+    euler_step_ref(const ItemDesc *__restrict__ items, int nitems, int jstep)
+{
+    const int lb = (int)blockIdx.x;
+    const ItemDesc &it = items[find_item(items, nitems, lb)];
+    if (jstep >= it.nsteps) return;
+    const int local = lb - it.block_begin;
+    const int nx = it.nx, ny = it.ny, nz = it.nz;
+    const int64_t npts = (int64_t)nx * ny * nz;
+    const int64_t idx = (int64_t)local * kRefThreads + threadIdx.x;
+    if (idx >= npts) return;
+    const int x = (int)(idx % nx), y = (int)((idx / nx) % ny), z = (int)(idx / ((int64_t)nx * ny));
+    const T *src;
+    T *dst;
+    pingpong<T>(it, jstep, it.nsteps, src, dst);
+    const double nu = nu_at(it, (double)(it.step0 + jstep) * it.dt);
+    const Wts<T, 1> w = coarse_weights<T>(it, nu);
+    T cen, mn[3][1], pn[3][1];
+    gather<T, 1>(src, x, y, z, nx, ny, nz, cen, mn, pn);
+    const T S = apply<T, 1>(w, cen, mn, pn);
+    dst[idx] = fmaT((T)it.dt, S, cen);
+}
+
+// ---------------------------------------------------------------------------
+// Variant registry
+// ---------------------------------------------------------------------------
+using FineLaunch = void (*)(const ItemDesc *, int, int, int, hipStream_t);
+using CoarseLaunch = void (*)(const ItemDesc *, int, int, int, hipStream_t);
+
+template <typename T, int R, int NXP, int NY, int BXT, int BY>
+void fine_launch(const ItemDesc *items, int nitems, int nblocks, int jstep, hipStream_t s)
+{
+    hipLaunchKernelGGL((rk4_step_fused<T, R, NXP, NY, BXT, BY>), dim3(nblocks), dim3(BXT * BY), 0, s, items,
+                       nitems, jstep);
+}
+
+template <typename T, int S, int NXP, int NY, int BXT, int BY>
+void coarse_launch(const ItemDesc *items, int nitems, int nblocks, int chunk, hipStream_t s)
+{
+    hipLaunchKernelGGL((euler_chunk_fused<T, S, NXP, NY, BXT, BY>), dim3(nblocks), dim3(BXT * BY), 0, s, items,
+                       nitems, chunk);
+}
+
+struct FineEntry {
+    VariantInfo info;
+    FineLaunch fn;
+};
+struct CoarseEntry {
+    VariantInfo info;
+    CoarseLaunch fn;
+};
+
+#define FINE_V(T, DT, R, NXP, NY, BXT, BY, NAME)                                                          \
+    FineEntry{VariantInfo{NAME, DT, 2 * R, BXT * NXP - 8 * R, BY * NY - 8 * R, NXP, BXT * BY, 1},       \
+              &fine_launch<T, R, NXP, NY, BXT, BY>}
+#define COARSE_V(T, DT, S, NXP, NY, BXT, BY, NAME)                                                        \
+    CoarseEntry{VariantInfo{NAME, DT, 0, BXT * NXP - 2 * S, BY * NY - 2 * S, NXP, BXT * BY, S},          \
+                &coarse_launch<T, S, NXP, NY, BXT, BY>}
+
+// index 0 and 1 are reserved (automatic, unfused reference)
+const FineEntry kFine[] = {
+    FINE_V(double, 2, 1, 2, 2, 20, 20, "rk4_f64_o2_t32x32_p2x2"),
+    FINE_V(double, 2, 1, 2, 2, 36, 12, "rk4_f64_o2_t64x16_p2x2"),
+    FINE_V(double, 2, 1, 1, 4, 40, 10, "rk4_f64_o2_t32x32_p1x4"),
+    FINE_V(float, 1, 1, 2, 2, 20, 20, "rk4_f32_o2_t32x32_p2x2"),
+    FINE_V(float, 1, 1, 2, 4, 36, 10, "rk4_f32_o2_t64x32_p2x4"),
+    FINE_V(float, 1, 1, 4, 2, 18, 20, "rk4_f32_o2_t64x32_p4x2"),
+    FINE_V(float, 1, 1, 1, 4, 40, 10, "rk4_f32_o2_t32x32_p1x4"),
+    FINE_V(double, 2, 2, 2, 1, 24, 32, "rk4_f64_o4_t32x16_p2x1"),
+    FINE_V(double, 2, 2, 1, 1, 40, 24, "rk4_f64_o4_t24x8_p1x1"),
+    FINE_V(float, 1, 2, 2, 2, 24, 16, "rk4_f32_o4_t32x16_p2x2"),
+    FINE_V(float, 1, 2, 1, 2, 48, 16, "rk4_f32_o4_t32x16_p1x2"),
+};
+
+const CoarseEntry kCoarse[] = {
+    COARSE_V(double, 2, 4, 2, 2, 20, 20, "euler4_f64_t32x32_p2x2"),
+    COARSE_V(double, 2, 2, 2, 2, 18, 18, "euler2_f64_t32x32_p2x2"),
+    COARSE_V(double, 2, 1, 1, 2, 34, 17, "euler1_f64_t32x32_p1x2"),
+    COARSE_V(float, 1, 4, 2, 2, 20, 20, "euler4_f32_t32x32_p2x2"),
+    COARSE_V(float, 1, 8, 2, 2, 24, 24, "euler8_f32_t32x32_p2x2"),
+    COARSE_V(float, 1, 2, 2, 2, 18, 18, "euler2_f32_t32x32_p2x2"),
+    COARSE_V(float, 1, 1, 1, 2, 34, 17, "euler1_f32_t32x32_p1x2"),
+    COARSE_V(double, 2, 4, 1, 4, 40, 10, "euler4_f64_t32x32_p1x4"),
+    COARSE_V(float, 1, 4, 1, 4, 40, 10, "euler4_f32_t32x32_p1x4"),
+};
+
+constexpr int kNumFine = (int)(sizeof(kFine) / sizeof(kFine[0]));
+constexpr int kNumCoarse = (int)(sizeof(kCoarse) / sizeof(kCoarse[0]));
+
+}  // namespace
+
+int fine_variant_count() { return kNumFine + 2; }
+int coarse_variant_count() { return kNumCoarse + 2; }
+
+const VariantInfo *fine_variant(int v)
+{
+    if (v < 2 || v >= kNumFine + 2) return nullptr;
+    return &kFine[v - 2].info;
+}
+
+const VariantInfo *coarse_variant(int v)
+{
+    if (v < 2 || v >= kNumCoarse + 2) return nullptr;
+    return &kCoarse[v - 2].info;
+}
+
+hipError_t launch_fine_step(int variant, int dtype, int order, const ItemDesc *items, int nitems, int nblocks,
+                            int jstep, hipStream_t s)
+{
+    if (nblocks <= 0) return hipSuccess;
+    if (variant == 1) {
+        for (int st = 1; st <= 4; ++st) {
+            if (dtype == 2) {
+                if (order == 4)
+                    hipLaunchKernelGGL((rk4_stage_ref<double, 2>), dim3(nblocks), dim3(kRefThreads), 0, s, items,
+                                       nitems, jstep, st);
+                else
+                    hipLaunchKernelGGL((rk4_stage_ref<double, 1>), dim3(nblocks), dim3(kRefThreads), 0, s, items,
+                                       nitems, jstep, st);
+            } else {
+                if (order == 4)
+                    hipLaunchKernelGGL((rk4_stage_ref<float, 2>), dim3(nblocks), dim3(kRefThreads), 0, s, items,
+                                       nitems, jstep, st);
+                else
+                    hipLaunchKernelGGL((rk4_stage_ref<float, 1>), dim3(nblocks), dim3(kRefThreads), 0, s, items,
+                                       nitems, jstep, st);
+            }
+        }
+        return hipGetLastError();
+    }
+    if (variant < 2 || variant >= kNumFine + 2) return hipErrorInvalidValue;
+    kFine[variant - 2].fn(items, nitems, nblocks, jstep, s);
+    return hipGetLastError();
+}
+
+hipError_t launch_coarse_chunk(int variant, int dtype, const ItemDesc *items, int nitems, int nblocks, int chunk,
+                               hipStream_t s)
+{
+    if (nblocks <= 0) return hipSuccess;
+    if (variant == 1) {
+        if (dtype == 2)
+            hipLaunchKernelGGL((euler_step_ref<double>), dim3(nblocks), dim3(kRefThreads), 0, s, items, nitems, chunk);
+        else
+            hipLaunchKernelGGL((euler_step_ref<float>), dim3(nblocks), dim3(kRefThreads), 0, s, items, nitems, chunk);
+        return hipGetLastError();
+    }
+    if (variant < 2 || variant >= kNumCoarse + 2) return hipErrorInvalidValue;
+    kCoarse[variant - 2].fn(items, nitems, nblocks, chunk, s);
+    return hipGetLastError();
+}
+
+}  // namespace pr

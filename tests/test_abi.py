@@ -1,0 +1,186 @@
+"""The C-ABI library loads, exports every declared symbol, and validates its
+arguments without a GPU (device work fails with PR_EDEVICE).  CPU only."""
+import ctypes
+import os
+import re
+
+import pytest
+
+import workloads as W
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _lib():
+    from paper_1409_8563_amd import _lib as L
+    return L
+
+
+def header_functions():
+    txt = open(os.path.join(ROOT, "include", "pr.h")).read()
+    txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+    return sorted(set(re.findall(r"\b(pr_[a-z0-9_]+)\s*\(", txt)))
+
+
+def test_header_and_binding_agree():
+    L = _lib()
+    assert header_functions() == sorted(L.EXPORTS)
+
+
+def test_library_exports_every_declared_symbol():
+    L = _lib()
+    so = ctypes.CDLL(L.LIB_PATH)
+    for name in header_functions():
+        assert hasattr(so, name), name
+
+
+def test_version_and_error_string():
+    L = _lib()
+    assert L.lib().pr_version().startswith(b"pr ")
+    assert isinstance(L.last_error(), str)
+
+
+def _status(fn, *args):
+    return fn(*args)
+
+
+@pytest.mark.parametrize("name", ["c2_128_fp64", "c3_256_mixed", "c5_512_mixed"])
+def test_literal_coarse_counts_rejected_stabilised_accepted(name):
+    """Forward Euler/upwind with the literal coarse step counts violates
+    Dt (sum|a|/h + 2 nu_max sum 1/h^2) <= 1; the raised counts satisfy it."""
+    import paper_1409_8563_amd as pr
+    p, _ = W.config(name)
+    rc, fm, cm = pr.check_stability(p)
+    assert rc == 0 and cm <= 0.9 + 1e-12 and fm <= 1.0 + 1e-12
+    p.nt_coarse = W.LITERAL_COARSE[name]
+    rc, fm, cm = pr.check_stability(p)
+    assert rc == _lib().PR_EUNSTABLE and cm > 1.5
+    L = _lib()
+    arr = (L.PrProblem * 1)(L.to_struct(p))
+    assert L.lib().pr_plan_workspace_bytes(arr, 1, 0) == 0
+    h = ctypes.c_void_p()
+    assert L.lib().pr_plan_create(arr, 1, 0, None, 0, ctypes.byref(h)) == L.PR_EUNSTABLE
+    p.flags |= W.ALLOW_UNSTABLE
+    arr = (L.PrProblem * 1)(L.to_struct(p))
+    assert L.lib().pr_plan_workspace_bytes(arr, 1, 0) > 0
+
+
+def test_coarse_margin_formula():
+    import paper_1409_8563_amd as pr
+    p, _ = W.config("c1_32_fp64")
+    _, _, cm = pr.check_stability(p)
+    expect = (p.T / p.nt_coarse) * W.coarse_bound(p.n, p.a, p.nu0 * 1.5)
+    assert abs(cm - expect) <= 1e-12 * expect
+
+
+def test_fine_margin_detects_unstable_rk4():
+    import paper_1409_8563_amd as pr
+    p = W.small_problem(n=(32, 32, 32), nu0=0.5, nf=1, nc=200, P=1, T=0.05)
+    rc, fm, _ = pr.check_stability(p)
+    assert fm > 1.0 and rc == _lib().PR_EUNSTABLE
+
+
+def test_batched_instances_all_stable():
+    import paper_1409_8563_amd as pr
+    for p, _ in W.batched_config(64):
+        rc, fm, cm = pr.check_stability(p)
+        assert rc == 0, (p.n, cm)
+
+
+def _sweep_rc(p, **kw):
+    L = _lib()
+    s = L.to_struct(p)
+    args = dict(dtype=2, batch=1, u_in=1 << 20, u_out=1 << 40, step0=(ctypes.c_int64 * 1)(0), nsteps=1,
+                ws=1 << 42, ws_bytes=1 << 40)
+    args.update(kw)
+    return L.lib().pr_fine_sweep(ctypes.byref(s), args["dtype"], args["batch"], ctypes.c_void_p(args["u_in"]),
+                                 ctypes.c_void_p(args["u_out"]), args["step0"], args["nsteps"],
+                                 ctypes.c_void_p(args["ws"]), args["ws_bytes"], None)
+
+
+def test_sweep_validation_without_device():
+    L = _lib()
+    p = W.small_problem(n=(16, 16, 16))
+    assert _sweep_rc(p) == L.PR_EDEVICE                      # valid request, no GPU here
+    assert _sweep_rc(p, dtype=3) == L.PR_EINVAL
+    assert _sweep_rc(p, batch=0) == L.PR_EINVAL
+    assert _sweep_rc(p, nsteps=-1) == L.PR_EINVAL
+    assert _sweep_rc(p, u_out=(1 << 20) + 16) == L.PR_EINVAL  # overlapping fields
+    assert _sweep_rc(p, u_out=(1 << 30) + 8) == L.PR_EINVAL   # misaligned
+    assert _sweep_rc(p, ws_bytes=16) == L.PR_ENOMEM
+    assert _sweep_rc(p, step0=(ctypes.c_int64 * 1)(-1)) == L.PR_EINVAL
+    bad = W.small_problem(n=(2, 16, 16))
+    assert _sweep_rc(bad) == L.PR_EINVAL
+    bad = W.small_problem(n=(16, 16, 16))
+    bad.nu0 = 0.0
+    assert _sweep_rc(bad) == L.PR_EINVAL
+    bad = W.small_problem(n=(16, 16, 16))
+    bad.nu_amp = 1.0
+    assert _sweep_rc(bad) == L.PR_EINVAL
+    bad = W.small_problem(n=(4, 16, 16), order=4)
+    assert _sweep_rc(bad) == L.PR_EINVAL
+    assert "n[0]" in L.last_error()
+
+
+def test_plan_validation():
+    L = _lib()
+    good = W.small_problem(n=(16, 16, 16), P=4, K=2)
+
+    def rc_for(*probs, mode=0):
+        arr = (L.PrProblem * len(probs))(*[L.to_struct(q) for q in probs])
+        h = ctypes.c_void_p()
+        return L.lib().pr_plan_create(arr, len(probs), mode, ctypes.c_void_p(1 << 40), 1 << 50, ctypes.byref(h))
+
+    assert rc_for(good) == L.PR_EDEVICE
+    bad = W.small_problem(n=(16, 16, 16), P=4, K=5)
+    assert rc_for(bad) == L.PR_EINVAL
+    bad = W.small_problem(n=(16, 16, 16), P=4, K=2)
+    bad.nt_fine = 10
+    assert rc_for(bad) == L.PR_EINVAL
+    other = W.small_problem(n=(16, 16, 16), P=4, K=1)
+    assert rc_for(good, other) == L.PR_EINVAL               # K differs
+    assert rc_for(good, mode=1 << 10) == L.PR_EINVAL
+    arr = (L.PrProblem * 1)(L.to_struct(good))
+    h = ctypes.c_void_p()
+    assert L.lib().pr_plan_create(arr, 1, 0, ctypes.c_void_p(1 << 40), 100, ctypes.byref(h)) == L.PR_ENOMEM
+
+
+def test_workspace_sizes():
+    """The largest single-instance workload fits in 288 GB of HBM."""
+    L = _lib()
+    for name, mode in (("c2_128_fp64", 0), ("c3_256_mixed", 1), ("c5_512_mixed", 1)):
+        p, _ = W.config(name)
+        arr = (L.PrProblem * 1)(L.to_struct(p))
+        nb = L.lib().pr_plan_workspace_bytes(arr, 1, mode)
+        n = p.npts
+        es = 4 if mode else 8
+        assert nb >= (p.P + 1) * n * 8 + 4 * p.P * n * es
+        assert nb < 288e9
+    insts = [q for q, _ in W.batched_config(64)]
+    arr = (L.PrProblem * len(insts))(*[L.to_struct(q) for q in insts])
+    assert 0 < L.lib().pr_plan_workspace_bytes(arr, len(insts), 1) < 64e9
+
+
+def test_defect_and_update_validation():
+    L = _lib()
+    assert L.lib().pr_parareal_update(10, 1, 3, 1, 1, 1, 1, None, None) == L.PR_EINVAL
+    assert L.lib().pr_parareal_update(10, 1, 2, None, 1, 1, 1, None, None) == L.PR_EINVAL
+    assert L.lib().pr_defect_norm(10, 1, 2, 1, 2, 1, 1, 1, 0, None) == L.PR_ENOMEM
+    assert L.lib().pr_defect_norm(0, 1, 2, 1, 2, 1, 1, 1, 1 << 20, None) == L.PR_EINVAL
+    assert L.lib().pr_defect_workspace_bytes(3) > 0
+
+
+def test_variant_registry():
+    import paper_1409_8563_amd as pr
+    L = _lib()
+    fine = pr.variants(0)
+    coarse = pr.variants(1)
+    assert len(fine) >= 4 and len(coarse) >= 4
+    for v in fine:
+        assert v["dtype"] in (1, 2) and v["order"] in (2, 4) and v["steps"] == 1
+        assert v["tile"][0] > 0 and v["tile"][1] > 0
+    for v in coarse:
+        assert v["order"] == 0 and v["steps"] >= 1
+    assert L.lib().pr_kernel_variant_name(0, 1) == b"rk4_unfused_reference"
+    assert L.lib().pr_set_kernel_variant(10 ** 6, 0) == L.PR_EINVAL
+    assert L.lib().pr_set_kernel_variant(0, 0) == 0

@@ -1,0 +1,385 @@
+"""GPU parity of the HIP path (through the C ABI) against the FP64 CPU oracle
+and the per-mode reference.  Bars: FP64 relative L2 <= 1e-12, FP32 relative
+L2 <= 1e-5 (against FP64), bitwise equality where the arithmetic is the same
+(kernel variants, tile shapes, batching, graph replay, slice skipping)."""
+import numpy as np
+import pytest
+
+import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+FP64_TOL = 1e-12
+FP32_TOL = 1e-5
+
+
+@pytest.fixture(scope="module")
+def pr():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_1409_8563_amd as prm
+    prm.lib()
+    prm.set_kernel_variant(0, 0)
+    yield prm
+    prm.set_kernel_variant(0, 0)
+
+
+def cuda(x, dtype=None):
+    import torch
+    t = torch.from_numpy(np.ascontiguousarray(x))
+    if dtype is not None:
+        t = t.to(dtype)
+    return t.cuda()
+
+
+def host(t):
+    import torch
+    torch.cuda.synchronize()
+    return t.detach().cpu().double().numpy()
+
+
+def rel_l2(a, b):
+    return float(np.sqrt(np.sum((a - b) ** 2) / np.sum(b ** 2)))
+
+
+def say(*a):
+    print(*a, flush=True)
+
+
+# ---------------------------------------------------------------------------
+# sweeps
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("n3", [(40, 36, 20), (37, 29, 23), (64, 33, 70)])
+@pytest.mark.parametrize("order", [2, 4])
+def test_fine_step_fp64(pr, orc, n3, order):
+    import torch
+    say("fine step fp64", n3, order)
+    p = W.small_problem(n=n3, a=(0.9, -0.6, 0.35), nu0=0.003, order=order, nf=8, P=4)
+    u = W.random_field(n3, 101)
+    ref = orc.rk4_step(p, 5, u)
+    got = host(pr.fine_sweep(p, cuda(u), 5, 1))
+    assert rel_l2(got, ref) <= FP64_TOL
+    assert np.max(np.abs(got - ref)) <= 1e-12 * np.max(np.abs(ref))
+
+
+def test_fine_sweep_batch_of_slices_fp64(pr, orc):
+    say("fine sweep batch fp64")
+    p = W.small_problem(n=(34, 30, 26), P=3, nf=5, nc=2)
+    u = np.stack([W.random_field(p.n, 110 + s) for s in range(p.P)])
+    got = host(pr.fine_sweep(p, cuda(u), [s * p.nf for s in range(p.P)], p.nf))
+    for s in range(p.P):
+        ref = orc.fine_steps(p, s * p.nf, p.nf, u[s])
+        assert rel_l2(got[s], ref) <= FP64_TOL, s
+
+
+@pytest.mark.parametrize("nsteps", [0, 1, 3, 7, 8])
+@pytest.mark.parametrize("a", [(0.9, -0.6, 0.0), (-0.3, 0.7, 1.1)])
+def test_coarse_sweep_fp64(pr, orc, nsteps, a):
+    say("coarse sweep fp64", nsteps, a)
+    p = W.small_problem(n=(36, 34, 22), a=a, nu0=0.004, P=2, nc=8)
+    u = W.random_field(p.n, 120)
+    got = host(pr.coarse_sweep(p, cuda(u), 3, nsteps))
+    ref = orc.coarse_steps(p, 3, nsteps, u)
+    if nsteps == 0:
+        assert np.array_equal(got, u)
+    else:
+        assert rel_l2(got, ref) <= FP64_TOL
+
+
+def test_fp32_sweeps_against_fp64_oracle(pr, orc):
+    import torch
+    say("fp32 sweeps")
+    p = W.small_problem(n=(48, 40, 36), a=(1.0, 0.5, 0.25), nu0=0.004, P=2, nf=16, nc=4)
+    modes = W.draw_modes(np.random.default_rng(130), 6, 4)
+    u = W.synth_u0(p.n, modes)
+    gf = host(pr.fine_sweep(p, cuda(u, torch.float32), 0, 16))
+    gc = host(pr.coarse_sweep(p, cuda(u, torch.float32), 0, 4))
+    assert rel_l2(gf, orc.fine_steps(p, 0, 16, u)) <= FP32_TOL
+    assert rel_l2(gc, orc.coarse_steps(p, 0, 4, u)) <= FP32_TOL
+
+
+def _applicable(pr, which, dtype, order, nx):
+    out = [1]
+    for v in pr.variants(which):
+        if v["dtype"] == dtype and (which == 1 or v["order"] == order) and nx % v["nxp"] == 0:
+            out.append(v["index"])
+    return out
+
+
+@pytest.mark.parametrize("dtype", [1, 2])
+@pytest.mark.parametrize("order", [2, 4])
+def test_fine_variants_bitwise_identical(pr, dtype, order):
+    """Every tile configuration and the unfused reference give the same bits:
+    the per-point arithmetic does not depend on tiling or schedule."""
+    import torch
+    tdt = torch.float64 if dtype == 2 else torch.float32
+    p = W.small_problem(n=(72, 52, 41), a=(0.7, -0.45, 0.3), nu0=0.002, order=order, P=2, nf=4)
+    u = cuda(W.random_field(p.n, 140), tdt)
+    outs = {}
+    try:
+        for v in _applicable(pr, 0, dtype, order, p.n[0]):
+            say("fine variant", v, dtype, order)
+            pr.set_kernel_variant(v, 0)
+            outs[v] = pr.fine_sweep(p, u, 3, 3)
+    finally:
+        pr.set_kernel_variant(0, 0)
+    base = outs[1]
+    assert len(outs) >= 2
+    for v, o in outs.items():
+        assert torch.equal(o, base), v
+
+
+@pytest.mark.parametrize("dtype", [1, 2])
+def test_coarse_variants_bitwise_identical(pr, dtype):
+    import torch
+    tdt = torch.float64 if dtype == 2 else torch.float32
+    p = W.small_problem(n=(66, 40, 37), a=(0.7, -0.45, 0.0), nu0=0.002, P=1, nc=13)
+    u = cuda(W.random_field(p.n, 150), tdt)
+    outs = {}
+    try:
+        for v in _applicable(pr, 1, dtype, 0, p.n[0]):
+            say("coarse variant", v, dtype)
+            pr.set_kernel_variant(0, v)
+            outs[v] = pr.coarse_sweep(p, u, 2, 13)
+    finally:
+        pr.set_kernel_variant(0, 0)
+    assert len(outs) >= 3
+    for v, o in outs.items():
+        assert torch.equal(o, outs[1]), v
+
+
+@pytest.mark.parametrize("dtype", [1, 2])
+def test_translation_equivariance_bitwise(pr, dtype):
+    import torch
+    say("translation", dtype)
+    tdt = torch.float64 if dtype == 2 else torch.float32
+    p = W.small_problem(n=(64, 48, 40), a=(0.8, -0.3, 0.5), P=2, nf=3, nc=3)
+    u = cuda(W.random_field(p.n, 160), tdt)
+    sh = (7, -5, 11)
+    a1 = pr.fine_sweep(p, torch.roll(u, sh, (0, 1, 2)).contiguous(), 1, 3)
+    a2 = torch.roll(pr.fine_sweep(p, u, 1, 3), sh, (0, 1, 2))
+    assert torch.equal(a1, a2)
+    b1 = pr.coarse_sweep(p, torch.roll(u, sh, (0, 1, 2)).contiguous(), 1, 5)
+    b2 = torch.roll(pr.coarse_sweep(p, u, 1, 5), sh, (0, 1, 2))
+    assert torch.equal(b1, b2)
+
+
+def test_update_and_defect_norm(pr, orc):
+    import torch
+    say("update/defect")
+    n3 = (30, 20, 17)
+    f, g, h = (W.random_field(n3, s) for s in (170, 171, 172))
+    for tdt in (torch.float64, torch.float32):
+        F, G, H = cuda(f, tdt), cuda(g, tdt), cuda(h, tdt)
+        lo = torch.empty_like(F)
+        u = host(pr.parareal_update(F, G, G, u_out_lo=lo))
+        assert np.array_equal(u, host(F))                    # G_new == G_old gives F exactly
+        assert torch.equal(lo, F)
+        u = host(pr.parareal_update(F, G, H))
+        Fd, Gd, Hd = host(F), host(G), host(H)
+        assert np.array_equal(u, Fd + (Gd - Hd))
+    x, r = W.random_field(n3, 173), W.random_field(n3, 174)
+    got = host(pr.defect_norm(cuda(np.stack([x, r])), cuda(np.stack([r, x])), batch=2))
+    for b, (xx, rr) in enumerate(((x, r), (r, x))):
+        ref = orc.norms(xx, rr)
+        assert got[b, 0] == ref[0] and got[b, 1] == ref[1]
+        assert abs(got[b, 2] - ref[2]) <= 1e-13 * ref[2] and abs(got[b, 3] - ref[3]) <= 1e-13 * ref[3]
+
+
+# ---------------------------------------------------------------------------
+# Parareal solves
+# ---------------------------------------------------------------------------
+
+def _solve(pr, probs, u0s, mode, ref=None):
+    plan = pr.Plan(probs, mode)
+    uT, log = plan.solve([cuda(u) for u in u0s], ref=ref)
+    states = [[host(plan.slice_state(i, n)) for n in range(probs[i].P + 1)] for i in range(len(probs))]
+    out = [host(x) for x in uT], log, states, plan
+    return out
+
+
+def test_parareal_c1_fp64_against_oracle(pr, orc):
+    say("parareal c1 fp64")
+    p, modes = W.config("c1_32_fp64")
+    u0 = W.synth_u0(p.n, modes)
+    _, olog, hist = orc.parareal(p, u0, K=p.K, history=True)
+    uT, log, states, plan = _solve(pr, [p], [u0], pr.PR_MODE_FP64)
+    for n in range(p.P + 1):
+        assert rel_l2(states[0][n], hist[p.K, n]) <= FP64_TOL, n
+    assert rel_l2(uT[0], hist[p.K, p.P]) <= FP64_TOL
+    # inter-iterate monitors agree with the oracle's
+    assert np.allclose(log[0][:, :8], olog, rtol=1e-9, atol=1e-14)
+    # K = P: the result is the GPU serial fine solution, bitwise
+    ser = host(pr.fine_sweep(p, cuda(u0), 0, p.nt_fine))
+    assert np.array_equal(uT[0], ser)
+
+
+def test_parareal_every_iterate_against_oracle(pr, orc):
+    """K = 0..P on a problem with odd n_x (one-point-per-thread kernels)."""
+    p = W.small_problem(n=(21, 18, 15), a=(0.6, 0.9, -0.4), nu0=0.01, P=3, nf=6, nc=2)
+    u0 = W.random_field(p.n, 180)
+    _, _, hist = orc.parareal(p, u0, K=p.P, history=True)
+    for K in range(p.P + 1):
+        say("parareal K", K)
+        p.K = K
+        uT, _, states, _ = _solve(pr, [p], [u0], pr.PR_MODE_FP64)
+        for n in range(p.P + 1):
+            assert rel_l2(states[0][n], hist[K, n]) <= FP64_TOL, (K, n)
+
+
+def test_parareal_modes_bitwise_identical(pr):
+    """Batched vs per-slice F, skipping converged slices, and HIP-graph replay
+    (several replays, with eager work in between) give identical bits."""
+    import torch
+    p = W.small_problem(n=(40, 24, 28), P=5, nf=4, nc=2, K=3)
+    u0 = W.random_field(p.n, 190)
+    say("modes: eager")
+    base, blog, bstates, _ = _solve(pr, [p], [u0], pr.PR_MODE_FP64)
+    say("modes: per-slice")
+    ps, plog, _, _ = _solve(pr, [p], [u0], pr.PR_MODE_FP64 | pr.PR_MODE_PER_SLICE)
+    assert np.array_equal(ps[0], base[0]) and np.array_equal(plog, blog)
+    q = W.small_problem(n=(40, 24, 28), P=5, nf=4, nc=2, K=3, flags=W.SKIP_CONVERGED)
+    say("modes: skip")
+    sk, slog, sstates, _ = _solve(pr, [q], [u0], pr.PR_MODE_FP64)
+    assert np.array_equal(sk[0], base[0])
+    for n in range(p.P + 1):
+        assert np.array_equal(sstates[0][n], bstates[0][n]), n
+    assert np.allclose(slog, blog, rtol=0, atol=0)
+    say("modes: graph")
+    plan = pr.Plan([p], pr.PR_MODE_FP64 | pr.PR_MODE_GRAPH)
+    x = cuda(u0)
+    for rep in range(3):
+        uT, glog = plan.solve([x])
+        scratch = torch.randn(1000, device="cuda").sum()   # eager work between replays
+        torch.cuda.synchronize()
+        assert np.array_equal(host(uT[0]), base[0]), rep
+        assert np.array_equal(glog, blog), rep
+        del scratch
+
+
+def test_parareal_mixed_against_oracle(pr, orc):
+    say("parareal mixed")
+    modes = W.draw_modes(np.random.default_rng(200), 8, 4)
+    p = W.small_problem(n=(48, 40, 32), a=(1.0, 0.5, 0.25), nu0=0.005, P=4, nf=16, nc=4, K=2)
+    u0 = W.synth_u0(p.n, modes)
+    U, olog = orc.parareal(p, u0, K=p.K)
+    uT, log, states, _ = _solve(pr, [p], [u0], pr.PR_MODE_MIXED)
+    assert rel_l2(uT[0], U[-1]) <= FP32_TOL
+    for n in range(p.P + 1):
+        assert rel_l2(states[0][n], U[n]) <= FP32_TOL, n
+
+
+def test_multi_instance_uneven(pr, orc):
+    """Instances of different sizes, coefficients and step counts in one plan:
+    each equals its own single-instance solve bitwise and the oracle to 1e-12."""
+    probs, u0s = [], []
+    for i, (n, nu0, a, nf, nc) in enumerate([(16, 0.01, (0.5, 0.3, -0.2), 4, 2), (24, 0.004, (-0.9, 0.2, 0.6), 6, 3),
+                                             (20, 0.006, (0.3, -0.8, 0.1), 5, 2)]):
+        p = W.small_problem(n=(n, n, n), a=a, nu0=nu0, P=4, nf=nf, nc=nc, K=2)
+        probs.append(p)
+        u0s.append(W.random_field(p.n, 210 + i))
+    for mode in (pr.PR_MODE_FP64, pr.PR_MODE_MIXED):
+        say("multi-instance mode", mode)
+        uT, log, _, _ = _solve(pr, probs, u0s, mode)
+        for i, p in enumerate(probs):
+            one, one_log, _, _ = _solve(pr, [p], [u0s[i]], mode)
+            assert np.array_equal(uT[i], one[0]), i
+            assert np.array_equal(log[i], one_log[0]), i
+            if mode == pr.PR_MODE_FP64:
+                U, _ = orc.parareal(p, u0s[i], K=p.K)
+                assert rel_l2(uT[i], U[-1]) <= FP64_TOL
+
+
+def test_reference_defect_and_early_stop(pr, orc):
+    import torch
+    p = W.small_problem(n=(24, 24, 24), P=4, nf=6, nc=2, K=4)
+    u0 = W.random_field(p.n, 220)
+    ufine = orc.serial_fine(p, u0)
+    say("ref defect")
+    uT, log, _, _ = _solve(pr, [p], [u0], pr.PR_MODE_FP64, ref=[cuda(ufine)])
+    _, _, hist = orc.parareal(p, u0, K=p.K, history=True)
+    for k in range(p.K):
+        nr = orc.norms(hist[k + 1, p.P], ufine)
+        assert abs(log[0, k, 8] - nr[0]) <= 1e-12 * nr[1] + 1e-300
+        assert abs(log[0, k, 9] - nr[1]) <= 1e-12 * nr[1]
+    assert log[0, p.K - 1, 8] <= 1e-13 * log[0, p.K - 1, 9]   # K = P: exact
+    say("early stop")
+    q = W.small_problem(n=(24, 24, 24), P=4, nf=6, nc=2, K=4, flags=W.EARLY_STOP)
+    q.tol = 1e30
+    plan = pr.Plan([q], pr.PR_MODE_FP64)
+    plan.solve([cuda(u0)])
+    assert plan.iterations() == 1
+    q.tol = 0.0
+    plan = pr.Plan([q], pr.PR_MODE_FP64)
+    plan.solve([cuda(u0)])
+    assert plan.iterations() == 4
+
+
+def test_nonfinite_input_is_reported(pr):
+    say("nonfinite")
+    p = W.small_problem(n=(16, 16, 16), P=2, nf=2, nc=1, K=1)
+    u0 = W.random_field(p.n, 230)
+    u0[3, 4, 5] = np.nan
+    plan = pr.Plan([p], pr.PR_MODE_FP64)
+    with pytest.raises(pr.PrError) as e:
+        plan.solve([cuda(u0)])
+    assert e.value.code == -6
+
+
+def test_autotune_keeps_results(pr):
+    import torch
+    p = W.small_problem(n=(64, 64, 64), P=2, nf=2, nc=2)
+    u = cuda(W.random_field(p.n, 240))
+    say("autotune")
+    before = pr.fine_sweep(p, u, 0, 2)
+    best = pr.autotune(p, 2, 1, 0)
+    assert best >= 2
+    after = pr.fine_sweep(p, u, 0, 2)
+    assert torch.equal(before, after)
+    bestc = pr.autotune(p, 2, 1, 1)
+    assert bestc >= 2
+
+
+# ---------------------------------------------------------------------------
+# full-size workloads, sampled against the per-mode reference
+# ---------------------------------------------------------------------------
+
+def _samples(p, count=4096, seed=7):
+    return np.random.default_rng(seed).integers(0, p.npts, size=count)
+
+
+def test_full_size_c2_fp64(pr):
+    """128^3, P = 16, K = 6, FP64 (the benchmark configuration): every slice
+    state at sampled points against the exact discrete solution."""
+    from oracle import spectral as S
+    say("c2 full size")
+    p, modes = W.config("c2_128_fp64")
+    u0 = W.synth_u0(p.n, modes)
+    ms = S.ModalSolution(p, modes)
+    plan = pr.Plan([p], pr.PR_MODE_FP64)
+    uT, log = plan.solve([cuda(u0)])
+    idx = _samples(p)
+    for n in range(p.P + 1):
+        got = host(plan.slice_state(0, n)).ravel()[idx]
+        ref = ms.iterate_points(p.K, n, idx)
+        assert rel_l2(got, ref) <= FP64_TOL, n
+    assert rel_l2(host(uT[0]).ravel()[idx], ms.iterate_points(p.K, p.P, idx)) <= FP64_TOL
+
+
+def test_full_size_c3_mixed(pr):
+    """256^3, P = 32, K = 6, FP32 sweeps with FP64 correction: every slice
+    state within 1e-5 relative L2 of the FP64 discrete solution at samples."""
+    from oracle import spectral as S
+    say("c3 full size")
+    p, modes = W.config("c3_256_mixed")
+    u0 = W.synth_u0(p.n, modes)
+    ms = S.ModalSolution(p, modes)
+    plan = pr.Plan([p], pr.PR_MODE_MIXED)
+    uT, log = plan.solve([cuda(u0)])
+    idx = _samples(p)
+    for n in range(p.P + 1):
+        got = host(plan.slice_state(0, n)).ravel()[idx]
+        ref = ms.iterate_points(p.K, n, idx)
+        assert rel_l2(got, ref) <= FP32_TOL, n
