@@ -11,6 +11,18 @@
 namespace pr {
 namespace {
 
+#define PR_GLOBAL __attribute__((address_space(1)))
+template <typename T>
+__device__ __forceinline__ const PR_GLOBAL T *G(const void *p)
+{
+    return (const PR_GLOBAL T *)p;
+}
+template <typename T>
+__device__ __forceinline__ PR_GLOBAL T *Gw(void *p)
+{
+    return (PR_GLOBAL T *)p;
+}
+
 struct PointArgs {
     const PointItem *table;  // device table, or nullptr to use `inl`
     PointItem inl;           // single inline item
@@ -70,24 +82,24 @@ __global__ void __launch_bounds__(kNormThreads) pointwise_kernel(PointArgs args,
     for (int64_t i = (int64_t)blockIdx.x * kNormThreads + threadIdx.x; i < n; i += stride) {
         double u;
         if (op == kOpCorrect) {
-            const double f = (double)((const T *)it.a)[i];
-            const double gn = (double)((const T *)it.b)[i];
-            const double go = (double)((const T *)it.c)[i];
+            const double f = (double)G<T>(it.a)[i];
+            const double gn = (double)G<T>(it.b)[i];
+            const double go = (double)G<T>(it.c)[i];
             u = f + (gn - go);
         } else if (op == kOpAssign) {
-            u = (double)((const T *)it.a)[i];
+            u = (double)G<T>(it.a)[i];
         } else {
-            u = ((const double *)it.a)[i];
+            u = G<double>(it.a)[i];
         }
         if (with_partials) {
-            const double d = u - it.u[i];
+            const double d = u - G<double>(it.u)[i];
             acc.mx = fmax(acc.mx, fabs(d));
             acc.mr = fmax(acc.mr, fabs(u));
             acc.sx += d * d;
             acc.sr += u * u;
         }
-        if (it.u) it.u[i] = u;
-        if (it.ulo) ((T *)it.ulo)[i] = (T)u;
+        if (it.u) Gw<double>(it.u)[i] = u;
+        if (it.ulo) Gw<T>(it.ulo)[i] = (T)u;
     }
     if (with_partials) {
         const Acc4 r = block_reduce(acc);
@@ -109,8 +121,8 @@ __global__ void __launch_bounds__(kNormThreads) defect_partials_kernel(PointArgs
     const int64_t n = it.npts;
     const int64_t stride = (int64_t)gridDim.x * kNormThreads;
     Acc4 acc{0.0, 0.0, 0.0, 0.0};
-    const TX *x = (const TX *)it.a;
-    const TR *r = (const TR *)it.b;
+    const PR_GLOBAL TX *x = G<TX>(it.a);
+    const PR_GLOBAL TR *r = G<TR>(it.b);
     for (int64_t i = (int64_t)blockIdx.x * kNormThreads + threadIdx.x; i < n; i += stride) {
         const double rv = (double)r[i];
         const double d = (double)x[i] - rv;
