@@ -54,6 +54,8 @@ def main():
     ap.add_argument("--config", default="c2_128_fp64")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-compare", action="store_true")
+    ap.add_argument("--copy-probe-mib", type=int, default=0,
+                    help="run one plain device-to-device copy of this size first (calibrates HBM counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path (time slices would shard "
@@ -75,6 +77,15 @@ def main():
     es = 4 if mixed else 8
     mode = pr.PR_MODE_MIXED if mixed else pr.PR_MODE_FP64
     log("config", args.config, "n", p.n, "P", p.P, "K", p.K, "nt_fine", p.nt_fine, "nt_coarse", p.nt_coarse)
+
+    if args.copy_probe_mib > 0:
+        nbytes = args.copy_probe_mib << 20
+        a = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
+        b = torch.empty_like(a)
+        b.copy_(a)
+        torch.cuda.synchronize()
+        log("copy probe: %d MiB device-to-device" % args.copy_probe_mib)
+        del a, b
 
     u0_np = W.synth_u0(p.n, modes)
     u0 = torch.from_numpy(u0_np).cuda()

@@ -182,6 +182,35 @@ __device__ __forceinline__ T apply(const Wts<T, R> &w, T cen, const T (&mn)[3][R
     return s;
 }
 
+// Wave-uniform values (weights computed from the step time) are moved to
+// scalar registers; VOP3 FMAs take one scalar operand, which frees VGPRs.
+__device__ __forceinline__ float uni(float x)
+{
+    return __builtin_bit_cast(float, __builtin_amdgcn_readfirstlane(__builtin_bit_cast(int, x)));
+}
+__device__ __forceinline__ double uni(double x)
+{
+    const long long b = __builtin_bit_cast(long long, x);
+    const int lo = __builtin_amdgcn_readfirstlane((int)(b & 0xffffffffll));
+    const int hi = __builtin_amdgcn_readfirstlane((int)(b >> 32));
+    return __builtin_bit_cast(double, ((long long)hi << 32) | (unsigned int)lo);
+}
+
+template <typename T, int R>
+__device__ __forceinline__ Wts<T, R> uni(const Wts<T, R> &w)
+{
+    Wts<T, R> o;
+    o.c = uni(w.c);
+#pragma unroll
+    for (int d = 0; d < 3; ++d)
+#pragma unroll
+        for (int k = 0; k < R; ++k) {
+            o.m[d][k] = uni(w.m[d][k]);
+            o.p[d][k] = uni(w.p[d][k]);
+        }
+    return o;
+}
+
 template <typename T>
 struct RK4Consts {
     T c1, c2, c3, b1, b2, b3, b4;
@@ -273,10 +302,17 @@ __global__ void __launch_bounds__(BXT *BY)
     const double nu1 = nu_at(it, t);
     const double nu2 = it.frozen ? nu1 : nu_at(it, t + 0.5 * dt);
     const double nu4 = it.frozen ? nu1 : nu_at(it, t + dt);
-    const Wts<T, R> w1 = fine_weights<T, R>(it, nu1);
-    const Wts<T, R> w2 = fine_weights<T, R>(it, nu2);
-    const Wts<T, R> w4 = fine_weights<T, R>(it, nu4);
-    const RK4Consts<T> kc = rk4_consts<T>(dt);
+    const Wts<T, R> w1 = uni(fine_weights<T, R>(it, nu1));
+    const Wts<T, R> w2 = uni(fine_weights<T, R>(it, nu2));
+    const Wts<T, R> w4 = uni(fine_weights<T, R>(it, nu4));
+    RK4Consts<T> kc = rk4_consts<T>(dt);
+    kc.c1 = uni(kc.c1);
+    kc.c2 = uni(kc.c2);
+    kc.c3 = uni(kc.c3);
+    kc.b1 = uni(kc.b1);
+    kc.b2 = uni(kc.b2);
+    kc.b3 = uni(kc.b3);
+    kc.b4 = uni(kc.b4);
 
     T ur[L][NY][NXP], y1[L][NY][NXP], y2[L][NY][NXP], y3[L][NY][NXP], ac[L][NY][NXP];
     T pf[NY][NXP];
@@ -468,8 +504,8 @@ __global__ void __launch_bounds__(BXT *BY)
         const int64_t j = (int64_t)chunk * S + s;
         const bool act = j < it.nsteps;
         const double nu = nu_at(it, (double)(it.step0 + j) * it.dt);
-        w[s] = coarse_weights<T>(it, nu);
-        dts[s] = act ? (T)it.dt : (T)0;
+        w[s] = uni(coarse_weights<T>(it, nu));
+        dts[s] = uni(act ? (T)it.dt : (T)0);
     }
 
     T f[S][L][NY][NXP];
