@@ -1,0 +1,72 @@
+"""The oracle's pins reject plausible mistakes: each case plants one mistake
+in a copy of oracle.c (on the CPU), builds it, and runs the pin that must
+catch it.  CPU only."""
+import os
+import shutil
+import subprocess
+import sys
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+# (name, original text, planted mistake, pin that must fail)
+MUTATIONS = [
+    ("advection sign", "out[c] = nu * lap - adv;", "out[c] = nu * lap + adv;",
+     "tests/test_oracle_operators.py::test_fine_rhs_order2_matches_dense"),
+    ("laplacian centre weight", "lap = (xp1 + xm1 - 2.0 * uc) / (hx * hx)", "lap = (xp1 + xm1 - 2.1 * uc) / (hx * hx)",
+     "tests/test_oracle_operators.py::test_fine_rhs_order2_matches_dense"),
+    ("x and y neighbours transposed",
+     "const double ym1 = u[((long)z * ny + wrap(y - 1, ny)) * nx + x];\n                    const double yp1",
+     "const double ym1 = u[((long)z * ny + y) * nx + wrap(x - 1, nx)];\n                    const double yp1",
+     "tests/test_oracle_operators.py::test_fine_rhs_order4_matches_dense"),
+    ("order-4 laplacian coefficient", "(-xp2 + 16.0 * xp1 - 30.0 * uc + 16.0 * xm1 - xm2)",
+     "(-xp2 + 16.0 * xp1 - 30.0 * uc + 15.0 * xm1 - xm2)",
+     "tests/test_oracle_operators.py::test_fine_rhs_order4_matches_dense"),
+    ("upwind branch swapped", "if (p->ax > 0.0) rhs -= p->ax * (uc - xm1) / hx;",
+     "if (p->ax < 0.0) rhs -= p->ax * (uc - xm1) / hx;",
+     "tests/test_oracle_operators.py::test_coarse_courant_one_is_exact_shift"),
+    ("RK4 middle stage time", "const double nu2 = p->nu_frozen ? nu1 : or_nu(p, t + 0.5 * dt);",
+     "const double nu2 = nu1;", "tests/test_oracle_time.py::test_rk4_time_dependent_nu_is_fourth_order"),
+    ("RK4 last stage time", "const double nu4 = p->nu_frozen ? nu1 : or_nu(p, t + dt);",
+     "const double nu4 = p->nu_frozen ? nu1 : or_nu(p, t + 0.5 * dt);",
+     "tests/test_oracle_time.py::test_rk4_time_dependent_nu_is_fourth_order"),
+    ("RK4 stage-3 increment", "y[i] = u[i] + dt * k3[i];", "y[i] = u[i] + 0.5 * dt * k3[i];",
+     "tests/test_oracle_time.py::test_rk4_constant_nu_is_taylor_polynomial"),
+    ("RK4 weights", "(k1[i] + 2.0 * k2[i] + 2.0 * k3[i] + k4[i])", "(k1[i] + 2.0 * k2[i] + 1.0 * k3[i] + 2.0 * k4[i])",
+     "tests/test_oracle_time.py::test_rk4_constant_nu_is_taylor_polynomial"),
+    ("Euler time index", "const double nu = or_nu(p, (double)j * Dt);",
+     "const double nu = or_nu(p, (double)(j + 1) * Dt);",
+     "tests/test_oracle_time.py::test_euler_step_definition_and_time_index"),
+    ("correction sign", "Unext[i] = fh[i] + (Gn[i] - go[i]);", "Unext[i] = fh[i] + (go[i] - Gn[i]);",
+     "tests/test_oracle_parareal.py::test_binomial_closed_form_constant_coefficients"),
+    ("stale G_old", "                go[i] = Gn[i];\n", "",
+     "tests/test_oracle_parareal.py::test_k_equals_p_is_serial_fine_bitwise"),
+    ("slice start index", "or_rk4_step(p, (long)s * nf + i, out, out, work);", "or_rk4_step(p, (long)i, out, out, work);",
+     "tests/test_oracle_time.py::test_slices_use_global_step_index"),
+]
+
+
+@pytest.fixture(scope="module")
+def sandbox(tmp_path_factory):
+    d = tmp_path_factory.mktemp("mut")
+    for sub in ("oracle", "workloads", "tests", "paper_1409_8563_amd"):
+        shutil.copytree(os.path.join(ROOT, sub), os.path.join(d, sub),
+                        ignore=shutil.ignore_patterns("*.so", "*.so.*", "_build", "__pycache__", "csrc"))
+    return str(d)
+
+
+@pytest.mark.parametrize("name,orig,bad,pin", MUTATIONS, ids=[m[0] for m in MUTATIONS])
+def test_pin_rejects_planted_mistake(sandbox, name, orig, bad, pin):
+    src_path = os.path.join(ROOT, "oracle", "oracle.c")
+    src = open(src_path).read()
+    assert orig in src, "mutation site not found: " + name
+    dst = os.path.join(sandbox, "oracle", "oracle.c")
+    open(dst, "w").write(src.replace(orig, bad, 1))
+    lib = os.path.join(sandbox, "oracle", "liboracle.so")
+    if os.path.exists(lib):
+        os.remove(lib)
+    r = subprocess.run([sys.executable, "-m", "pytest", "-x", "-q", "-p", "no:cacheprovider", pin],
+                       cwd=sandbox, capture_output=True, text=True, timeout=600)
+    assert r.returncode != 0, "planted mistake '%s' was not caught by %s" % (name, pin)
+    assert "failed" in r.stdout

@@ -93,9 +93,11 @@ def test_rk4_frozen_nu_is_first_order_in_nu_variation(orc):
 def test_euler_step_definition_and_time_index(orc):
     n3 = (4, 5, 3)
     a = (-0.3, 0.6, 0.2)
-    p = W.small_problem(n=n3, a=a, nu0=0.02, P=2, nc=3)
+    # 10 coarse steps per period of nu: nu(j Dt) differs from nu((j +- 1) Dt)
+    p = W.small_problem(n=n3, a=a, nu0=0.02, P=2, nc=5)
     Dt = p.T / p.nt_coarse
     j = 4
+    assert len({round(math.sin(p.nu_omega * i * Dt), 12) for i in (j - 1, j, j + 1)}) == 3
     nu = p.nu0 * (1 + p.nu_amp * math.sin(p.nu_omega * j * Dt))
     M = np.eye(np.prod(n3)) + Dt * dense_coarse(n3, a, nu)
     u = W.random_field(n3, 22)
