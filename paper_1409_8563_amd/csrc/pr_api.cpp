@@ -14,6 +14,7 @@
 #include <complex>
 #include <cstdarg>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <map>
 #include <mutex>
@@ -261,9 +262,15 @@ void fill_item(ItemDesc &it, const pr_problem &p, bool fine)
 
 // Tile layout of a set of items for a variant; block ranges are assigned in
 // item order.  Returns the total number of blocks.
+int g_blocks_per_cu = 0;  // launch-size target of the tile layout (0: default)
+
 int layout(std::vector<ItemDesc> &items, const VariantInfo *vi, bool ref, int zmin)
 {
-    const int target = 4 * std::max(g_num_cus, 1);
+    if (g_blocks_per_cu == 0) {
+        const char *e = getenv("PR_BLOCKS_PER_CU");
+        g_blocks_per_cu = e ? std::max(1, atoi(e)) : 4;
+    }
+    const int target = g_blocks_per_cu * std::max(g_num_cus, 1);
     if (ref) {
         int b = 0;
         for (auto &it : items) {
