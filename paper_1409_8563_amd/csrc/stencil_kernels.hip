@@ -1163,6 +1163,10 @@ const FineEntry kFine[] = {
     FINE_1B(float, 1, 4, 2, 18, 20, "rk4b_f32_t64x32_p4x2"),
     FINE_1B(float, 1, 2, 2, 20, 20, "rk4b_f32_t32x32_p2x2"),
     FINE_1B(float, 1, 1, 4, 40, 10, "rk4b_f32_t32x32_p1x4"),
+    FINE_1B(double, 2, 2, 1, 20, 40, "rk4b_f64_t32x32_p2x1"),
+    FINE_1B(double, 2, 1, 2, 40, 20, "rk4b_f64_t32x32_p1x2"),
+    FINE_1B(float, 1, 2, 2, 36, 20, "rk4b_f32_t64x32_p2x2"),
+    FINE_1B(float, 1, 4, 1, 18, 40, "rk4b_f32_t64x32_p4x1"),
 };
 
 const CoarseEntry kCoarse[] = {
