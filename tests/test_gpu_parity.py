@@ -350,6 +350,12 @@ def _samples(p, count=4096, seed=7):
     return np.random.default_rng(seed).integers(0, p.npts, size=count)
 
 
+def _at(t, idx):
+    """Values of a device field at flat indices, gathered on the device."""
+    import torch
+    return host(t.reshape(-1)[torch.from_numpy(idx).cuda()])
+
+
 def test_full_size_c2_fp64(pr):
     """128^3, P = 16, K = 6, FP64 (the benchmark configuration): every slice
     state at sampled points against the exact discrete solution."""
@@ -362,10 +368,10 @@ def test_full_size_c2_fp64(pr):
     uT, log = plan.solve([cuda(u0)])
     idx = _samples(p)
     for n in range(p.P + 1):
-        got = host(plan.slice_state(0, n)).ravel()[idx]
+        got = _at(plan.slice_state(0, n), idx)
         ref = ms.iterate_points(p.K, n, idx)
         assert rel_l2(got, ref) <= FP64_TOL, n
-    assert rel_l2(host(uT[0]).ravel()[idx], ms.iterate_points(p.K, p.P, idx)) <= FP64_TOL
+    assert rel_l2(_at(uT[0], idx), ms.iterate_points(p.K, p.P, idx)) <= FP64_TOL
 
 
 def test_full_size_c3_mixed(pr):
@@ -380,7 +386,7 @@ def test_full_size_c3_mixed(pr):
     uT, log = plan.solve([cuda(u0)])
     idx = _samples(p)
     for n in range(p.P + 1):
-        got = host(plan.slice_state(0, n)).ravel()[idx]
+        got = _at(plan.slice_state(0, n), idx)
         ref = ms.iterate_points(p.K, n, idx)
         assert rel_l2(got, ref) <= FP32_TOL, n
 
@@ -417,3 +423,50 @@ def test_paper_setup_fourth_order(pr):
         d_ref = np.max(np.abs(it - fine)) / np.max(np.abs(fine))
         assert abs(d_gpu - d_ref) <= 1e-3 * d_ref, (k, d_gpu, d_ref)
     assert log[0, 2, 8] / log[0, 2, 9] < 0.1 * gold["eps_fine"]["omega_100"]
+
+
+def test_full_size_c4_batched(pr):
+    """64 uneven instances (48^3..128^3, own a and nu0, P = 8, K = 3) in one
+    mixed-precision plan: every instance's final state within 1e-5 of its
+    exact discrete solution at sampled points; one instance bitwise equal
+    to its own single-instance solve."""
+    import torch
+    from oracle import spectral as S
+    insts = W.batched_config(64)
+    probs = [p for p, _ in insts]
+    say("c4 batched: %d instances" % len(probs))
+    u0s = [cuda(W.synth_u0(p.n, m)) for p, m in insts]
+    plan = pr.Plan(probs, pr.PR_MODE_MIXED)
+    uT, log = plan.solve(u0s)
+    for i, (p, m) in enumerate(insts):
+        idx = _samples(p, count=1024, seed=i)
+        ms = S.ModalSolution(p, m)
+        got = _at(uT[i], idx)
+        assert rel_l2(got, ms.iterate_points(p.K, p.P, idx)) <= FP32_TOL, (i, p.n)
+    del plan
+    torch.cuda.empty_cache()
+    j = next(i for i, p in enumerate(probs) if p.n[0] == 96)
+    one = pr.Plan([probs[j]], pr.PR_MODE_MIXED)
+    uj, _ = one.solve([u0s[j]])
+    assert torch.equal(uj[0], uT[j])
+
+
+def test_full_size_c5_mixed(pr):
+    """The largest workload: 512^3, P = 32, K = 5, FP32 sweeps (all slice
+    states resident, ~110 GB): every slice state within 1e-5 relative L2 of
+    the FP64 discrete solution at sampled points."""
+    import torch
+    from oracle import spectral as S
+    say("c5 full size")
+    p, modes = W.config("c5_512_mixed")
+    u0 = cuda(W.synth_u0(p.n, modes))
+    plan = pr.Plan([p], pr.PR_MODE_MIXED)
+    uT, log = plan.solve([u0])
+    ms = S.ModalSolution(p, modes)
+    idx = _samples(p, count=2048)
+    for n in range(0, p.P + 1, 4):
+        got = _at(plan.slice_state(0, n), idx)
+        assert rel_l2(got, ms.iterate_points(p.K, n, idx)) <= FP32_TOL, n
+    assert rel_l2(_at(uT[0], idx), ms.iterate_points(p.K, p.P, idx)) <= FP32_TOL
+    del plan
+    torch.cuda.empty_cache()
