@@ -453,10 +453,11 @@ __global__ void __launch_bounds__(BXT *BY)
 // neighbours are read as aligned NXP-vectors (whole neighbour groups), which
 // keeps lanes on consecutive LDS addresses.
 // ---------------------------------------------------------------------------
-template <typename T, int NXP, int NY, int BXT, int BY>
+template <typename T, int NXP, int NY, int BXT, int BY, int PD>
 __global__ void __launch_bounds__(BXT *BY)
     rk4_step_fused1b(const ItemDesc *__restrict__ items, int nitems, int jstep)
 {
+    static_assert(4 % PD == 0, "prefetch depth must divide the unroll");
     constexpr int R = 1;
     constexpr int H = 4;
     constexpr int EX = BXT * NXP, EY = BY * NY;
@@ -520,15 +521,15 @@ __global__ void __launch_bounds__(BXT *BY)
     kc.b4 = uni(kc.b4);
 
     T ur[L][NY][NXP], y1[L][NY][NXP], y2[L][NY][NXP], y3[L][NY][NXP], ac[L][NY][NXP];
-    T pf[NY][NXP];
+    T pf[PD][NY][NXP];   // planes p .. p+PD-1 in flight (prefetch ring)
 
-    auto load_plane = [&](int p) {
+    auto load_plane = [&](int p, T(&dstp)[NY][NXP]) {
         const T *base = src + (size_t)wrapi(p, nz) * nxy;
 #pragma unroll
         for (int iy = 0; iy < NY; ++iy) {
             const Vec<T, NXP> v = gld<Vec<T, NXP>>(base + rowoff[iy]);
 #pragma unroll
-            for (int ix = 0; ix < NXP; ++ix) pf[iy][ix] = v.v[ix];
+            for (int ix = 0; ix < NXP; ++ix) dstp[iy][ix] = v.v[ix];
         }
     };
 
@@ -584,8 +585,8 @@ __global__ void __launch_bounds__(BXT *BY)
 #pragma unroll
         for (int iy = 0; iy < NY; ++iy)
 #pragma unroll
-            for (int ix = 0; ix < NXP; ++ix) ur[slot<L>(M, 0)][iy][ix] = pf[iy][ix];
-        load_plane(p + 1);
+            for (int ix = 0; ix < NXP; ++ix) ur[slot<L>(M, 0)][iy][ix] = pf[M % PD][iy][ix];
+        load_plane(p + PD, pf[M % PD]);
         put(ic<0>{}, ic<WS>{}, ur[slot<L>(M, 0)]);
 
         T S[NY][NXP];
@@ -650,7 +651,8 @@ __global__ void __launch_bounds__(BXT *BY)
 
     const int pstart = z0 - 4;
     const int niter = (zend - z0) + 8;
-    load_plane(pstart);
+#pragma unroll
+    for (int d = 0; d < PD; ++d) load_plane(pstart + d, pf[d]);
     for (int pb = 0; pb < niter; pb += L) {
         [&]<int... Ms>(std::integer_sequence<int, Ms...>) {
             (body(ic<Ms>{}, pstart + pb + Ms), ...);
@@ -662,10 +664,11 @@ __global__ void __launch_bounds__(BXT *BY)
 // Fused forward Euler chunk with one barrier per z plane (same scheme as
 // rk4_step_fused1b: stage outputs go to LDS and are read one iteration later).
 // ---------------------------------------------------------------------------
-template <typename T, int S, int NXP, int NY, int BXT, int BY>
+template <typename T, int S, int NXP, int NY, int BXT, int BY, int PD>
 __global__ void __launch_bounds__(BXT *BY)
     euler_chunk_fused1b(const ItemDesc *__restrict__ items, int nitems, int chunk)
 {
+    static_assert(6 % PD == 0, "prefetch depth must divide the unroll");
     constexpr int H = S;
     constexpr int EX = BXT * NXP, EY = BY * NY;
     constexpr int TX = EX - 2 * H, TY = EY - 2 * H;
@@ -724,15 +727,15 @@ __global__ void __launch_bounds__(BXT *BY)
     }
 
     T f[S][L][NY][NXP];
-    T pf[NY][NXP];
+    T pf[PD][NY][NXP];
 
-    auto load_plane = [&](int p) {
+    auto load_plane = [&](int p, T(&dstp)[NY][NXP]) {
         const T *base = src + (size_t)wrapi(p, nz) * nxy;
 #pragma unroll
         for (int iy = 0; iy < NY; ++iy) {
             const Vec<T, NXP> v = gld<Vec<T, NXP>>(base + rowoff[iy]);
 #pragma unroll
-            for (int ix = 0; ix < NXP; ++ix) pf[iy][ix] = v.v[ix];
+            for (int ix = 0; ix < NXP; ++ix) dstp[iy][ix] = v.v[ix];
         }
     };
 
@@ -745,12 +748,12 @@ __global__ void __launch_bounds__(BXT *BY)
             Vec<T, NXP> wv;
 #pragma unroll
             for (int ix = 0; ix < NXP; ++ix) {
-                f[0][slot<L>(M, 0)][iy][ix] = pf[iy][ix];
-                wv.v[ix] = pf[iy][ix];
+                f[0][slot<L>(M, 0)][iy][ix] = pf[M % PD][iy][ix];
+                wv.v[ix] = pf[M % PD][iy][ix];
             }
             *reinterpret_cast<Vec<T, NXP> *>(&lds[0][WS][1 + ry0 + iy][CO + cx0]) = wv;
         }
-        load_plane(p + 1);
+        load_plane(p + PD, pf[M % PD]);
 
         [&]<int... Ss>(std::integer_sequence<int, Ss...>) {
             (
@@ -816,7 +819,8 @@ __global__ void __launch_bounds__(BXT *BY)
 
     const int pstart = z0 - S;
     const int niter = (zend - z0) + 2 * S;
-    load_plane(pstart);
+#pragma unroll
+    for (int d = 0; d < PD; ++d) load_plane(pstart + d, pf[d]);
     for (int pb = 0; pb < niter; pb += U) {
         [&]<int... Ms>(std::integer_sequence<int, Ms...>) {
             (body(ic<Ms>{}, pstart + pb + Ms), ...);
@@ -1100,17 +1104,17 @@ void fine_launch(const ItemDesc *items, int nitems, int nblocks, int jstep, hipS
                        nitems, jstep);
 }
 
-template <typename T, int NXP, int NY, int BXT, int BY>
+template <typename T, int NXP, int NY, int BXT, int BY, int PD>
 void fine_launch_1b(const ItemDesc *items, int nitems, int nblocks, int jstep, hipStream_t s)
 {
-    hipLaunchKernelGGL((rk4_step_fused1b<T, NXP, NY, BXT, BY>), dim3(nblocks), dim3(BXT * BY), 0, s, items, nitems,
-                       jstep);
+    hipLaunchKernelGGL((rk4_step_fused1b<T, NXP, NY, BXT, BY, PD>), dim3(nblocks), dim3(BXT * BY), 0, s, items,
+                       nitems, jstep);
 }
 
-template <typename T, int S, int NXP, int NY, int BXT, int BY>
+template <typename T, int S, int NXP, int NY, int BXT, int BY, int PD>
 void coarse_launch_1b(const ItemDesc *items, int nitems, int nblocks, int chunk, hipStream_t s)
 {
-    hipLaunchKernelGGL((euler_chunk_fused1b<T, S, NXP, NY, BXT, BY>), dim3(nblocks), dim3(BXT * BY), 0, s, items,
+    hipLaunchKernelGGL((euler_chunk_fused1b<T, S, NXP, NY, BXT, BY, PD>), dim3(nblocks), dim3(BXT * BY), 0, s, items,
                        nitems, chunk);
 }
 
@@ -1133,12 +1137,12 @@ struct CoarseEntry {
 #define FINE_V(T, DT, R, NXP, NY, BXT, BY, NAME)                                                          \
     FineEntry{VariantInfo{NAME, DT, 2 * R, BXT * NXP - 8 * R, BY * NY - 8 * R, NXP, BXT * BY, 1},       \
               &fine_launch<T, R, NXP, NY, BXT, BY>}
-#define FINE_1B(T, DT, NXP, NY, BXT, BY, NAME)                                                           \
+#define FINE_1B(T, DT, NXP, NY, BXT, BY, PD, NAME)                                                       \
     FineEntry{VariantInfo{NAME, DT, 2, BXT * NXP - 8, BY * NY - 8, NXP, BXT * BY, 1},                  \
-              &fine_launch_1b<T, NXP, NY, BXT, BY>}
-#define COARSE_1B(T, DT, S, NXP, NY, BXT, BY, NAME)                                                       \
+              &fine_launch_1b<T, NXP, NY, BXT, BY, PD>}
+#define COARSE_1B(T, DT, S, NXP, NY, BXT, BY, PD, NAME)                                                   \
     CoarseEntry{VariantInfo{NAME, DT, 0, BXT * NXP - 2 * S, BY * NY - 2 * S, NXP, BXT * BY, S},          \
-                &coarse_launch_1b<T, S, NXP, NY, BXT, BY>}
+                &coarse_launch_1b<T, S, NXP, NY, BXT, BY, PD>}
 #define COARSE_V(T, DT, S, NXP, NY, BXT, BY, NAME)                                                        \
     CoarseEntry{VariantInfo{NAME, DT, 0, BXT * NXP - 2 * S, BY * NY - 2 * S, NXP, BXT * BY, S},          \
                 &coarse_launch<T, S, NXP, NY, BXT, BY>}
@@ -1156,17 +1160,22 @@ const FineEntry kFine[] = {
     FINE_V(double, 2, 2, 1, 1, 40, 24, "rk4_f64_o4_t24x8_p1x1"),
     FINE_V(float, 1, 2, 2, 2, 24, 16, "rk4_f32_o4_t32x16_p2x2"),
     FINE_V(float, 1, 2, 1, 2, 48, 16, "rk4_f32_o4_t32x16_p1x2"),
-    FINE_1B(double, 2, 2, 2, 20, 20, "rk4b_f64_t32x32_p2x2"),
-    FINE_1B(double, 2, 1, 4, 40, 10, "rk4b_f64_t32x32_p1x4"),
-    FINE_1B(double, 2, 2, 2, 36, 12, "rk4b_f64_t64x16_p2x2"),
-    FINE_1B(float, 1, 2, 4, 36, 10, "rk4b_f32_t64x32_p2x4"),
-    FINE_1B(float, 1, 4, 2, 18, 20, "rk4b_f32_t64x32_p4x2"),
-    FINE_1B(float, 1, 2, 2, 20, 20, "rk4b_f32_t32x32_p2x2"),
-    FINE_1B(float, 1, 1, 4, 40, 10, "rk4b_f32_t32x32_p1x4"),
-    FINE_1B(double, 2, 2, 1, 20, 40, "rk4b_f64_t32x32_p2x1"),
-    FINE_1B(double, 2, 1, 2, 40, 20, "rk4b_f64_t32x32_p1x2"),
-    FINE_1B(float, 1, 2, 2, 36, 20, "rk4b_f32_t64x32_p2x2"),
-    FINE_1B(float, 1, 4, 1, 18, 40, "rk4b_f32_t64x32_p4x1"),
+    FINE_1B(double, 2, 2, 2, 20, 20, 1, "rk4b_f64_t32x32_p2x2"),
+    FINE_1B(double, 2, 2, 2, 20, 20, 2, "rk4b_f64_t32x32_p2x2_d2"),
+    FINE_1B(double, 2, 2, 2, 20, 20, 4, "rk4b_f64_t32x32_p2x2_d4"),
+    FINE_1B(double, 2, 1, 4, 40, 10, 2, "rk4b_f64_t32x32_p1x4_d2"),
+    FINE_1B(double, 2, 2, 2, 36, 12, 2, "rk4b_f64_t64x16_p2x2_d2"),
+    FINE_1B(double, 2, 2, 1, 20, 40, 2, "rk4b_f64_t32x32_p2x1_d2"),
+    FINE_1B(double, 2, 2, 1, 20, 40, 4, "rk4b_f64_t32x32_p2x1_d4"),
+    FINE_1B(double, 2, 1, 2, 40, 20, 2, "rk4b_f64_t32x32_p1x2_d2"),
+    FINE_1B(float, 1, 2, 4, 36, 10, 2, "rk4b_f32_t64x32_p2x4_d2"),
+    FINE_1B(float, 1, 4, 2, 18, 20, 2, "rk4b_f32_t64x32_p4x2_d2"),
+    FINE_1B(float, 1, 2, 2, 20, 20, 2, "rk4b_f32_t32x32_p2x2_d2"),
+    FINE_1B(float, 1, 1, 4, 40, 10, 2, "rk4b_f32_t32x32_p1x4_d2"),
+    FINE_1B(float, 1, 2, 2, 36, 20, 1, "rk4b_f32_t64x32_p2x2"),
+    FINE_1B(float, 1, 2, 2, 36, 20, 2, "rk4b_f32_t64x32_p2x2_d2"),
+    FINE_1B(float, 1, 2, 2, 36, 20, 4, "rk4b_f32_t64x32_p2x2_d4"),
+    FINE_1B(float, 1, 4, 1, 18, 40, 2, "rk4b_f32_t64x32_p4x1_d2"),
 };
 
 const CoarseEntry kCoarse[] = {
@@ -1179,10 +1188,11 @@ const CoarseEntry kCoarse[] = {
     COARSE_V(float, 1, 1, 1, 2, 34, 17, "euler1_f32_t32x32_p1x2"),
     COARSE_V(double, 2, 4, 1, 4, 40, 10, "euler4_f64_t32x32_p1x4"),
     COARSE_V(float, 1, 4, 1, 4, 40, 10, "euler4_f32_t32x32_p1x4"),
-    COARSE_1B(double, 2, 4, 2, 2, 20, 20, "euler4b_f64_t32x32_p2x2"),
-    COARSE_1B(double, 2, 2, 2, 2, 18, 18, "euler2b_f64_t32x32_p2x2"),
-    COARSE_1B(float, 1, 4, 2, 2, 20, 20, "euler4b_f32_t32x32_p2x2"),
-    COARSE_1B(float, 1, 8, 2, 2, 24, 16, "euler8b_f32_t32x16_p2x2"),
+    COARSE_1B(double, 2, 4, 2, 2, 20, 20, 2, "euler4b_f64_t32x32_p2x2_d2"),
+    COARSE_1B(double, 2, 2, 2, 2, 18, 18, 2, "euler2b_f64_t32x32_p2x2_d2"),
+    COARSE_1B(float, 1, 4, 2, 2, 20, 20, 2, "euler4b_f32_t32x32_p2x2_d2"),
+    COARSE_1B(float, 1, 8, 2, 2, 24, 16, 2, "euler8b_f32_t32x16_p2x2_d2"),
+    COARSE_1B(double, 2, 4, 2, 2, 20, 20, 3, "euler4b_f64_t32x32_p2x2_d3"),
 };
 
 constexpr int kNumFine = (int)(sizeof(kFine) / sizeof(kFine[0]));
