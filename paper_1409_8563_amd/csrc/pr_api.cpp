@@ -154,11 +154,36 @@ void margins(const pr_problem &p, double *fm, double *cm)
     *fm = worst;
 }
 
+// Margins depend only on the grid, a, nu(t) bounds and step sizes; sweeps are
+// called many times with the same problem, so results are memoised.
+std::mutex g_margin_mu;
+std::map<std::vector<double>, std::pair<double, double>> g_margin_cache;
+
+void margins_cached(const pr_problem &p, double *fm, double *cm)
+{
+    const std::vector<double> key = {(double)p.n[0], (double)p.n[1], (double)p.n[2], p.a[0], p.a[1], p.a[2],
+                                     p.nu0, p.nu_amp, p.T, (double)p.nt_fine, (double)p.nt_coarse,
+                                     (double)p.fine_order};
+    {
+        std::lock_guard<std::mutex> lk(g_margin_mu);
+        auto it = g_margin_cache.find(key);
+        if (it != g_margin_cache.end()) {
+            *fm = it->second.first;
+            *cm = it->second.second;
+            return;
+        }
+    }
+    margins(p, fm, cm);
+    std::lock_guard<std::mutex> lk(g_margin_mu);
+    if (g_margin_cache.size() > 4096) g_margin_cache.clear();
+    g_margin_cache[key] = {*fm, *cm};
+}
+
 int stability_guard(const pr_problem &p, bool fine, bool coarse)
 {
     if (p.flags & PR_ALLOW_UNSTABLE) return PR_OK;
     double fm = 0, cm = 0;
-    margins(p, &fm, &cm);
+    margins_cached(p, &fm, &cm);
     if (fine && fm > 1.0 + 1e-12)
         return fail(PR_EUNSTABLE, "fine RK4 step unstable: max |R(dt mu)| = %.6g > 1", fm);
     if (coarse && cm > 1.0 + 1e-12)
@@ -847,7 +872,7 @@ int pr_check_stability(const pr_problem *prob, double *fine_margin, double *coar
     int rc = validate_problem(prob, false);
     if (rc) return rc;
     double fm = 0, cm = 0;
-    margins(*prob, &fm, &cm);
+    margins_cached(*prob, &fm, &cm);
     if (fine_margin) *fine_margin = fm;
     if (coarse_margin) *coarse_margin = cm;
     if (fm > 1.0 + 1e-12 || cm > 1.0 + 1e-12)
