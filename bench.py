@@ -149,11 +149,17 @@ def main():
         plan_ps = pr.Plan([p], pr.PR_MODE_FP64 | pr.PR_MODE_PER_SLICE)
         t_plain = timed(lambda: plan_ps.solve([u0], uT=[uT], want_log=False))
         del plan_ps
+        q = W.Problem(**dict(p.__dict__))
+        q.flags |= W.SKIP_CONVERGED
+        plan_sk = pr.Plan([q], mode)
+        t_skip = timed(lambda: plan_sk.solve([u0], uT=[uT], want_log=False))
+        del plan_sk
         t_serial = timed(lambda: pr.fine_sweep(p, u64, 0, p.nt_fine, u_out=out64))
         t_coarse = timed(lambda: pr.coarse_sweep(p, u64, 0, p.nt_coarse, u_out=out64))
         tau = (t_coarse / p.nt_coarse) / (t_serial / p.nt_fine)
         extra = {
             "time_to_solution_ms": {"parareal_batched": round(t_batched, 3),
+                                    "parareal_batched_skip_converged": round(t_skip, 3),
                                     "parareal_plain_fp64_per_slice": round(t_plain, 3),
                                     "serial_fine_fp64": round(t_serial, 3)},
             "batched_vs_plain_fp64_speedup": round(t_plain / t_batched, 3),

@@ -228,11 +228,10 @@ int pick_fine_default(const pr_problem &p, int dtype)
     const bool even = p.n[0] % 2 == 0;
     const char *name;
     if (dtype == PR_FP64)
-        name = order == 4 ? (even ? "rk4_f64_o4_t32x16_p2x1" : "rk4_f64_o4_t24x8_p1x1")
-                          : (even ? "rk4_f64_o2_t32x32_p2x2" : "rk4_f64_o2_t32x32_p1x4");
+        name = order == 4 ? (even ? "rk4_f64_o4_t32x16_p2x1" : "rk4_f64_o4_t24x8_p1x1") : "rk4b_f64_t32x32_p1x2_d2";
     else
         name = order == 4 ? (even ? "rk4_f32_o4_t32x16_p2x2" : "rk4_f32_o4_t32x16_p1x2")
-                          : (even ? "rk4_f32_o2_t64x32_p2x4" : "rk4_f32_o2_t32x32_p1x4");
+                          : (even ? "rk4b_f32_t64x32_p2x2_d2" : "rk4b_f32_t32x32_p1x4_d2");
     return find_fine(name);
 }
 
@@ -250,8 +249,8 @@ int pick_fine(const pr_problem &p, int dtype)
 int pick_coarse_default(const pr_problem &p, int dtype)
 {
     const bool even = p.n[0] % 2 == 0;
-    const char *name = dtype == PR_FP64 ? (even ? "euler4_f64_t32x32_p2x2" : "euler4_f64_t32x32_p1x4")
-                                        : (even ? "euler4_f32_t32x32_p2x2" : "euler4_f32_t32x32_p1x4");
+    const char *name = dtype == PR_FP64 ? (even ? "euler4b_f64_t32x32_p2x2_d2" : "euler4b_f64_t32x32_p1x4_d2")
+                                        : (even ? "euler4b_f32_t32x32_p2x2_d2" : "euler4b_f32_t32x32_p1x4_d2");
     return find_coarse(name);
 }
 
@@ -293,7 +292,7 @@ int layout(std::vector<ItemDesc> &items, const VariantInfo *vi, bool ref, int zm
 {
     if (g_blocks_per_cu == 0) {
         const char *e = getenv("PR_BLOCKS_PER_CU");
-        g_blocks_per_cu = e ? std::max(1, atoi(e)) : 4;
+        g_blocks_per_cu = e ? std::max(1, atoi(e)) : 1;
     }
     const int target = g_blocks_per_cu * std::max(g_num_cus, 1);
     if (ref) {

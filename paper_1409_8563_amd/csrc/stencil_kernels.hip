@@ -1193,6 +1193,8 @@ const CoarseEntry kCoarse[] = {
     COARSE_1B(float, 1, 4, 2, 2, 20, 20, 2, "euler4b_f32_t32x32_p2x2_d2"),
     COARSE_1B(float, 1, 8, 2, 2, 24, 16, 2, "euler8b_f32_t32x16_p2x2_d2"),
     COARSE_1B(double, 2, 4, 2, 2, 20, 20, 3, "euler4b_f64_t32x32_p2x2_d3"),
+    COARSE_1B(double, 2, 4, 1, 4, 40, 10, 2, "euler4b_f64_t32x32_p1x4_d2"),
+    COARSE_1B(float, 1, 4, 1, 4, 40, 10, 2, "euler4b_f32_t32x32_p1x4_d2"),
 };
 
 constexpr int kNumFine = (int)(sizeof(kFine) / sizeof(kFine[0]));
