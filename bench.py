@@ -25,6 +25,12 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
 
+# HBM bytes per batched fused-RK4 launch measured with rocprofv3 FETCH_SIZE /
+# WRITE_SIZE (scaled by the plain-copy calibration), for the kernel variant
+# and workload they were taken on (profiles/*_hbm_counters.md).  Reported
+# only while the plan still launches that variant.
+MEASURED_TRAFFIC = {("rk4b_f64_t32x32_p1x2_d2", "c2_128_fp64"): 558024704}
+
 
 def log(*a):
     print("[bench]", *a, file=sys.stderr, flush=True)
@@ -130,6 +136,8 @@ def main():
     bytes_per_launch = 2 * es * lups_per_launch
     achieved = bytes_per_launch / avg_launch_s / 1e9
     dk = [float(lg[0, k, 8] / lg[0, k, 9]) for k in range(p.K)]
+    fine_variant, coarse_variant = plan.kernel_variants()
+    traffic = MEASURED_TRAFFIC.get((fine_variant, args.config))
 
     extra = {}
     if not args.no_compare:
@@ -193,8 +201,9 @@ def main():
                                                            "FP32 sweeps + FP64 correction" if mixed else "FP64"),
                    "grid": list(p.n), "P": p.P, "K": p.K, "nt_fine": p.nt_fine, "nt_coarse": p.nt_coarse},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
-                     "kernel": "rk4_step_fused", "avg_launch_us": round(avg_launch_s * 1e6, 2),
+                     "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
+                     "kernel": "rk4_step_fused1b (%s)" % fine_variant, "coarse_kernel": coarse_variant,
+                     "avg_launch_us": round(avg_launch_s * 1e6, 2),
                      "algorithmic_bytes_per_launch": int(bytes_per_launch)},
         "cpu_baseline": cpu,
         "defect_dk": [float("%.3e" % d) for d in dk],

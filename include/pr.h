@@ -199,6 +199,10 @@ int pr_parareal_solve(pr_plan *plan, const double *const *u0, double *const *uT,
 /* Iterations performed by the last solve (< K only with PR_EARLY_STOP). */
 int pr_plan_iterations(const pr_plan *plan);
 
+/* Kernel variants the plan launches for F and G (HOST outputs, may be NULL);
+ * names via pr_kernel_variant_name. */
+int pr_plan_kernel_variants(const pr_plan *plan, int32_t *fine_variant, int32_t *coarse_variant);
+
 /*
  * pr_plan_timings -- phase times of the last solve of a PR_MODE_TIMED plan
  * (HOST out[6]): {F ms, G-chain ms (coarse sweeps and corrections), start-up

@@ -186,6 +186,12 @@ class Plan:
     def iterations(self):
         return lib().pr_plan_iterations(self._h)
 
+    def kernel_variants(self):
+        """(fine, coarse) kernel variant names launched by this plan."""
+        f, c = ctypes.c_int32(), ctypes.c_int32()
+        check(lib().pr_plan_kernel_variants(self._h, ctypes.byref(f), ctypes.byref(c)))
+        return (lib().pr_kernel_variant_name(0, f.value).decode(), lib().pr_kernel_variant_name(1, c.value).decode())
+
     def timings(self):
         out = (ctypes.c_double * 6)()
         check(lib().pr_plan_timings(self._h, out))

@@ -1047,6 +1047,14 @@ void pr_plan_destroy(pr_plan *plan)
 
 int pr_plan_iterations(const pr_plan *plan) { return plan ? plan->iters_done : 0; }
 
+int pr_plan_kernel_variants(const pr_plan *plan, int32_t *fine_variant, int32_t *coarse_variant)
+{
+    if (!plan) return fail(PR_EINVAL, "plan is NULL");
+    if (fine_variant) *fine_variant = plan->fine_v;
+    if (coarse_variant) *coarse_variant = plan->coarse_v;
+    return PR_OK;
+}
+
 int pr_plan_slice_state(const pr_plan *plan, int32_t inst, int32_t n, const double **out)
 {
     if (!plan || !out) return fail(PR_EINVAL, "NULL argument");
