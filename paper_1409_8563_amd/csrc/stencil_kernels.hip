@@ -1048,6 +1048,173 @@ __global__ void __launch_bounds__(BXT *BY)
 }
 
 // ---------------------------------------------------------------------------
+template <typename T, int S, int NXP, int NY, int BXT, int BY, int PD>
+__global__ void __launch_bounds__(BXT *BY)
+    euler_chunk_fused1c(const ItemDesc *__restrict__ items, int nitems, int chunk)
+{
+    static_assert(6 % PD == 0, "prefetch depth must divide the unroll");
+    constexpr int H = S;
+    constexpr int EX = BXT * NXP, EY = BY * NY;
+    constexpr int TX = EX - 2 * H, TY = EY - 2 * H;
+    constexpr int L = 3;                                   // z-ring length
+    constexpr int U = 6;                                   // unroll: ring phase and LDS slot parity
+    constexpr int CO = NXP;
+    constexpr int LX = EX + 2 * CO + (sizeof(T) == 8 ? 2 : 4);
+    constexpr int LY = EY + 2;
+    static_assert(TX > 0 && TY > 0, "tile too small for the halo");
+    __shared__ __align__(16) T ldsA[S][LY][LX];
+    __shared__ __align__(16) T ldsB[S][LY][LX];
+
+    const int lb = xcd_remap((int)blockIdx.x, (int)gridDim.x);
+    const ItemDesc &it = items[find_item(items, nitems, lb)];
+    const int nchunks = (it.nsteps + S - 1) / S;
+    if (chunk >= nchunks) return;
+    const int local = lb - it.block_begin;
+    if (local < 0 || local >= it.nblocks) return;
+
+    const int nx = it.nx, ny = it.ny, nz = it.nz;
+    const int txt = local % it.tiles_x;
+    const int rest = local / it.tiles_x;
+    const int tyt = rest % it.tiles_y;
+    const int zc = rest / it.tiles_y;
+    const int x0 = txt * TX, y0 = tyt * TY;
+    const int z0 = zc * it.tz;
+    const int zend = min(z0 + it.tz, nz);
+
+    const T *src;
+    T *dst;
+    pingpong<T>(it, chunk, nchunks, src, dst);
+
+    const int tid = (int)threadIdx.x;
+    const int txi = tid % BXT, tyi = tid / BXT;
+    const int cx0 = txi * NXP, ry0 = tyi * NY;
+    const int gx0 = wrapi(x0 - H + cx0, nx);
+    int rowoff[NY];
+    bool yok[NY];
+#pragma unroll
+    for (int iy = 0; iy < NY; ++iy) {
+        const int ry = ry0 + iy;
+        rowoff[iy] = wrapi(y0 - H + ry, ny) * nx + gx0;
+        yok[iy] = (ry >= H) && (ry < H + TY) && (y0 + ry - H < ny);
+    }
+    const bool xok = (cx0 >= H) && (cx0 < H + TX) && (x0 + cx0 - H < nx);
+    const int nxy = nx * ny;
+
+    Wts<T, 1> w[S];
+    T dts[S];
+#pragma unroll
+    for (int s = 0; s < S; ++s) {
+        const int64_t j = (int64_t)chunk * S + s;
+        const bool act = j < it.nsteps;
+        const double nu = nu_at(it, (double)(it.step0 + j) * it.dt);
+        w[s] = uni(coarse_weights<T>(it, nu));
+        dts[s] = uni(act ? (T)it.dt : (T)0);
+    }
+
+    T f[S][L][NY][NXP];
+    T pf[PD][NY][NXP];
+
+    auto load_plane = [&](int p, T(&dstp)[NY][NXP]) {
+        const T *base = src + (size_t)wrapi(p, nz) * nxy;
+#pragma unroll
+        for (int iy = 0; iy < NY; ++iy) {
+            const Vec<T, NXP> v = gld<Vec<T, NXP>>(base + rowoff[iy]);
+#pragma unroll
+            for (int ix = 0; ix < NXP; ++ix) dstp[iy][ix] = v.v[ix];
+        }
+    };
+
+    auto body = [&](auto Mc, int p) {
+        constexpr int M = decltype(Mc)::value;
+        constexpr int WS = M & 1, RS = (M + 1) & 1;
+        __syncthreads();
+#pragma unroll
+        for (int iy = 0; iy < NY; ++iy) {
+            Vec<T, NXP> wv;
+#pragma unroll
+            for (int ix = 0; ix < NXP; ++ix) {
+                f[0][slot<L>(M, 0)][iy][ix] = pf[M % PD][iy][ix];
+                wv.v[ix] = pf[M % PD][iy][ix];
+            }
+            T(*lw)[LX] = WS == 0 ? ldsA[0] : ldsB[0];
+            *reinterpret_cast<Vec<T, NXP> *>(&lw[1 + ry0 + iy][CO + cx0]) = wv;
+        }
+        load_plane(p + PD, pf[M % PD]);
+
+        [&]<int... Ss>(std::integer_sequence<int, Ss...>) {
+            (
+                [&] {
+                    constexpr int s = Ss + 1;          // stage s computes plane p - s from f[s-1]
+                    constexpr int sc = slot<L>(M, s);
+                    // branch-free: fill iterations compute planes no stored output needs
+                    {
+                        const T(*lr)[LX] = RS == 0 ? ldsA[s - 1] : ldsB[s - 1];
+                        const Vec<T, NXP> up = *reinterpret_cast<const Vec<T, NXP> *>(&lr[ry0][CO + cx0]);
+                        const Vec<T, NXP> dn = *reinterpret_cast<const Vec<T, NXP> *>(&lr[1 + ry0 + NY][CO + cx0]);
+                        T res[NY][NXP];
+#pragma unroll
+                        for (int iy = 0; iy < NY; ++iy) {
+                            const Vec<T, NXP> lf = *reinterpret_cast<const Vec<T, NXP> *>(&lr[1 + ry0 + iy][CO + cx0 - NXP]);
+                            const Vec<T, NXP> rt = *reinterpret_cast<const Vec<T, NXP> *>(&lr[1 + ry0 + iy][CO + cx0 + NXP]);
+#pragma unroll
+                            for (int ix = 0; ix < NXP; ++ix) {
+                                T mn[3][1], pn[3][1];
+                                mn[0][0] = (ix >= 1) ? f[s - 1][sc][iy][ix - 1] : lf.v[NXP - 1];
+                                pn[0][0] = (ix + 1 < NXP) ? f[s - 1][sc][iy][ix + 1] : rt.v[0];
+                                mn[1][0] = (iy >= 1) ? f[s - 1][sc][iy - 1][ix] : up.v[ix];
+                                pn[1][0] = (iy + 1 < NY) ? f[s - 1][sc][iy + 1][ix] : dn.v[ix];
+                                mn[2][0] = f[s - 1][slot<L>(M, s + 1)][iy][ix];
+                                pn[2][0] = f[s - 1][slot<L>(M, s - 1)][iy][ix];
+                                const T cen = f[s - 1][sc][iy][ix];
+                                const T Sv = apply<T, 1>(w[s - 1], cen, mn, pn);
+                                res[iy][ix] = fmaT(dts[s - 1], Sv, cen);
+                            }
+                        }
+                        if constexpr (s < S) {
+#pragma unroll
+                            for (int iy = 0; iy < NY; ++iy) {
+                                Vec<T, NXP> wv;
+#pragma unroll
+                                for (int ix = 0; ix < NXP; ++ix) {
+                                    f[s][slot<L>(M, s)][iy][ix] = res[iy][ix];
+                                    wv.v[ix] = res[iy][ix];
+                                }
+                                T(*lw)[LX] = WS == 0 ? ldsA[s] : ldsB[s];
+                                *reinterpret_cast<Vec<T, NXP> *>(&lw[1 + ry0 + iy][CO + cx0]) = wv;
+                            }
+                        } else {
+                            const int q = p - S;
+                            if (xok && q >= z0 && q < zend) {
+                                T *obase = dst + (size_t)q * nxy;
+#pragma unroll
+                                for (int iy = 0; iy < NY; ++iy) {
+                                    if (yok[iy]) {
+                                        Vec<T, NXP> v;
+#pragma unroll
+                                        for (int ix = 0; ix < NXP; ++ix) v.v[ix] = res[iy][ix];
+                                        gst<Vec<T, NXP>>(obase + rowoff[iy], v);
+                                    }
+                                }
+                            }
+                        }
+                    }
+                }(),
+                ...);
+        }(std::make_integer_sequence<int, S>{});
+    };
+
+    const int pstart = z0 - S;
+    const int niter = (zend - z0) + 2 * S;
+#pragma unroll
+    for (int d = 0; d < PD; ++d) load_plane(pstart + d, pf[d]);
+    for (int pb = 0; pb < niter; pb += U) {
+        [&]<int... Ms>(std::integer_sequence<int, Ms...>) {
+            (body(ic<Ms>{}, pstart + pb + Ms), ...);
+        }(std::make_integer_sequence<int, U>{});
+    }
+}
+
+// ---------------------------------------------------------------------------
 // Fused forward Euler chunk: S steps of Algorithm 2 per HBM pass.  Steps past
 // the end of a field's sweep are exact identities (zero step size).
 // ---------------------------------------------------------------------------
@@ -1366,6 +1533,15 @@ struct CoarseEntry {
 #define FINE_1B(T, DT, NXP, NY, BXT, BY, PD, NAME)                                                       \
     FineEntry{VariantInfo{NAME, DT, 2, BXT * NXP - 8, BY * NY - 8, NXP, BXT * BY, 1},                  \
               &fine_launch_1b<T, NXP, NY, BXT, BY, PD>}
+template <typename T, int S, int NXP, int NY, int BXT, int BY, int PD>
+void coarse_launch_1c(const ItemDesc *items, int nitems, int nblocks, int chunk, hipStream_t s)
+{
+    hipLaunchKernelGGL((euler_chunk_fused1c<T, S, NXP, NY, BXT, BY, PD>), dim3(nblocks), dim3(BXT * BY), 0, s, items,
+                       nitems, chunk);
+}
+#define COARSE_1C(T, DT, S, NXP, NY, BXT, BY, PD, NAME)                                                   \
+    CoarseEntry{VariantInfo{NAME, DT, 0, BXT * NXP - 2 * S, BY * NY - 2 * S, NXP, BXT * BY, S},          \
+                &coarse_launch_1c<T, S, NXP, NY, BXT, BY, PD>}
 #define FINE_1C(T, DT, NXP, NY, BXT, BY, PD, PAD, NAME)                                                  \
     FineEntry{VariantInfo{NAME, DT, 2, BXT * NXP - 8, BY * NY - 8, NXP, BXT * BY, 1},                  \
               &fine_launch_1c<T, NXP, NY, BXT, BY, PD, PAD>}
@@ -1435,6 +1611,11 @@ const CoarseEntry kCoarse[] = {
     COARSE_1B(double, 2, 4, 2, 2, 20, 20, 3, "euler4b_f64_t32x32_p2x2_d3"),
     COARSE_1B(double, 2, 4, 1, 4, 40, 10, 2, "euler4b_f64_t32x32_p1x4_d2"),
     COARSE_1B(float, 1, 4, 1, 4, 40, 10, 2, "euler4b_f32_t32x32_p1x4_d2"),
+    COARSE_1C(double, 2, 4, 2, 2, 20, 20, 2, "euler4c_f64_t32x32_p2x2"),
+    COARSE_1C(double, 2, 4, 1, 2, 40, 20, 2, "euler4c_f64_t32x32_p1x2"),
+    COARSE_1C(double, 2, 2, 2, 2, 18, 18, 2, "euler2c_f64_t32x32_p2x2"),
+    COARSE_1C(float, 1, 4, 2, 2, 20, 20, 2, "euler4c_f32_t32x32_p2x2"),
+    COARSE_1C(float, 1, 2, 2, 2, 18, 18, 2, "euler2c_f32_t32x32_p2x2"),
 };
 
 constexpr int kNumFine = (int)(sizeof(kFine) / sizeof(kFine[0]));
