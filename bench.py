@@ -60,6 +60,8 @@ def main():
     ap.add_argument("--config", default="c2_128_fp64")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-compare", action="store_true")
+    ap.add_argument("--mixed-config", default="c3_256_mixed",
+                    help="workload of the batched-FP32 vs plain-per-slice-FP64 comparison ('' to skip)")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="run one plain device-to-device copy of this size first (calibrates HBM counters)")
     args = ap.parse_args()
@@ -175,6 +177,40 @@ def main():
             "S_bound_eq_speedup": round(costmodel.speedup_bound(p.P, p.K, p.nc / p.nf, tau), 3),
         }
         log("comparisons", extra)
+        if args.mixed_config:
+            # the mixed-precision target: batched FP32-sweep Parareal against plain
+            # per-slice FP64 Parareal on the same workload, both at their errors
+            # against the exact discrete FP64 solution (per-mode reference)
+            from oracle import spectral as S
+            pm, mm = W.config(args.mixed_config)
+            um = torch.from_numpy(W.synth_u0(pm.n, mm)).cuda()
+            uTm = torch.empty_like(um)
+            idx = np.random.default_rng(7).integers(0, pm.npts, size=4096)
+            ref = S.ModalSolution(pm, mm).iterate_points(pm.K, pm.P, idx)
+            tix = torch.from_numpy(idx).cuda()
+
+            def err_of():
+                torch.cuda.synchronize()
+                got = uTm.reshape(-1)[tix].cpu().numpy()
+                return float(np.sqrt(np.sum((got - ref) ** 2) / np.sum(ref ** 2)))
+
+            plan_m = pr.Plan([pm], pr.PR_MODE_MIXED)
+            t_m = timed(lambda: plan_m.solve([um], uT=[uTm], want_log=False), reps=1)
+            e_m = err_of()
+            del plan_m
+            torch.cuda.empty_cache()
+            plan_p = pr.Plan([pm], pr.PR_MODE_FP64 | pr.PR_MODE_PER_SLICE)
+            t_p = timed(lambda: plan_p.solve([um], uT=[uTm], want_log=False), reps=1)
+            e_p = err_of()
+            del plan_p
+            torch.cuda.empty_cache()
+            extra["mixed_vs_plain_fp64"] = {
+                "workload": "%s: %dx%dx%d, P=%d, K=%d" % (args.mixed_config, pm.n[0], pm.n[1], pm.n[2], pm.P, pm.K),
+                "batched_fp32_sweeps_ms": round(t_m, 2), "plain_fp64_per_slice_ms": round(t_p, 2),
+                "speedup": round(t_p / t_m, 3),
+                "rel_l2_vs_fp64_discrete": {"batched_fp32_sweeps": float("%.3e" % e_m),
+                                            "plain_fp64_per_slice": float("%.3e" % e_p)}}
+            log("mixed comparison", extra["mixed_vs_plain_fp64"])
 
     cpu = None
     if not args.no_cpu_baseline:
