@@ -27,9 +27,18 @@ HBM_PEAK_GBS = 8000.0
 
 # HBM bytes per batched fused-RK4 launch measured with rocprofv3 FETCH_SIZE /
 # WRITE_SIZE (scaled by the plain-copy calibration), for the kernel variant
-# and workload they were taken on (profiles/*_hbm_counters.md).  Reported
+# and workload they were taken on (the hbm_counters summaries).  Reported
 # only while the plan still launches that variant.
-MEASURED_TRAFFIC = {("rk4b_f64_t32x32_p1x2_d2", "c2_128_fp64"): 558024704}
+MEASURED_TRAFFIC = {("rk4w_f64_x128_y8_p2x1_w16", "c2_128_fp64"): 558019729}
+
+
+def kernel_of(variant):
+    """HIP kernel that a fused fine variant launches."""
+    for prefix, kernel in (("rk4w_", "rk4_step_rows"), ("rk4b_", "rk4_step_fused1b"), ("rk4c_", "rk4_step_fused1c"),
+                           ("rk4_", "rk4_step_fused")):
+        if variant.startswith(prefix):
+            return kernel
+    return "rk4_stage_ref"
 
 
 def log(*a):
@@ -178,38 +187,39 @@ def main():
         }
         log("comparisons", extra)
         if args.mixed_config:
-            # the mixed-precision target: batched FP32-sweep Parareal against plain
-            # per-slice FP64 Parareal on the same workload, both at their errors
-            # against the exact discrete FP64 solution (per-mode reference)
-            from oracle import spectral as S
+            # batched FP32-sweep Parareal against plain per-slice FP64 Parareal on
+            # the same workload.  Errors are taken on the device against the FP64
+            # serial fine solution of the library's own FP64 path (that path is
+            # checked against the CPU oracle by the parity tests), and between the
+            # two Parareal results (the FP32 sweeps' own rounding).
             pm, mm = W.config(args.mixed_config)
             um = torch.from_numpy(W.synth_u0(pm.n, mm)).cuda()
-            uTm = torch.empty_like(um)
-            idx = np.random.default_rng(7).integers(0, pm.npts, size=4096)
-            ref = S.ModalSolution(pm, mm).iterate_points(pm.K, pm.P, idx)
-            tix = torch.from_numpy(idx).cuda()
+            u_fine64 = pr.fine_sweep(pm, um, 0, pm.nt_fine)
+            uT_mixed = torch.empty_like(um)
+            uT_plain = torch.empty_like(um)
 
-            def err_of():
-                torch.cuda.synchronize()
-                got = uTm.reshape(-1)[tix].cpu().numpy()
-                return float(np.sqrt(np.sum((got - ref) ** 2) / np.sum(ref ** 2)))
+            def errs(x, r):
+                o = pr.defect_norm(x, r).cpu().numpy()[0]
+                return {"max_abs": float("%.3e" % o[0]), "rel_l2": float("%.3e" % np.sqrt(o[2] / o[3]))}
 
             plan_m = pr.Plan([pm], pr.PR_MODE_MIXED)
-            t_m = timed(lambda: plan_m.solve([um], uT=[uTm], want_log=False), reps=1)
-            e_m = err_of()
+            t_m = timed(lambda: plan_m.solve([um], uT=[uT_mixed], want_log=False), reps=1)
             del plan_m
             torch.cuda.empty_cache()
             plan_p = pr.Plan([pm], pr.PR_MODE_FP64 | pr.PR_MODE_PER_SLICE)
-            t_p = timed(lambda: plan_p.solve([um], uT=[uTm], want_log=False), reps=1)
-            e_p = err_of()
+            t_p = timed(lambda: plan_p.solve([um], uT=[uT_plain], want_log=False), reps=1)
             del plan_p
             torch.cuda.empty_cache()
             extra["mixed_vs_plain_fp64"] = {
-                "workload": "%s: %dx%dx%d, P=%d, K=%d" % (args.mixed_config, pm.n[0], pm.n[1], pm.n[2], pm.P, pm.K),
+                "workload": "%s: %dx%dx%d, P=%d, K=%d, %d fine / %d coarse steps" % (
+                    args.mixed_config, pm.n[0], pm.n[1], pm.n[2], pm.P, pm.K, pm.nt_fine, pm.nt_coarse),
                 "batched_fp32_sweeps_ms": round(t_m, 2), "plain_fp64_per_slice_ms": round(t_p, 2),
                 "speedup": round(t_p / t_m, 3),
-                "rel_l2_vs_fp64_discrete": {"batched_fp32_sweeps": float("%.3e" % e_m),
-                                            "plain_fp64_per_slice": float("%.3e" % e_p)}}
+                "error_vs_fp64_serial_fine": {"batched_fp32_sweeps": errs(uT_mixed, u_fine64),
+                                              "plain_fp64_per_slice": errs(uT_plain, u_fine64)},
+                "batched_fp32_vs_plain_fp64_parareal": errs(uT_mixed, uT_plain)}
+            del um, u_fine64, uT_mixed, uT_plain
+            torch.cuda.empty_cache()
             log("mixed comparison", extra["mixed_vs_plain_fp64"])
 
     cpu = None
@@ -238,7 +248,7 @@ def main():
                    "grid": list(p.n), "P": p.P, "K": p.K, "nt_fine": p.nt_fine, "nt_coarse": p.nt_coarse},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
-                     "kernel": "rk4_step_fused1b (%s)" % fine_variant, "coarse_kernel": coarse_variant,
+                     "kernel": "%s (%s)" % (kernel_of(fine_variant), fine_variant), "coarse_kernel": coarse_variant,
                      "avg_launch_us": round(avg_launch_s * 1e6, 2),
                      "algorithmic_bytes_per_launch": int(bytes_per_launch)},
         "cpu_baseline": cpu,

@@ -231,9 +231,10 @@ int pr_kernel_variant_count(int32_t which /* 0 fine, 1 coarse */);
 const char *pr_kernel_variant_name(int32_t which, int32_t variant);
 /* Properties of a fused variant (HOST outputs, any may be NULL): field dtype,
  * fine stencil order (0 for coarse), output tile, x points per thread (n_x
- * must be a multiple), Euler steps fused per launch (1 for fine). */
+ * must be a multiple), Euler steps fused per launch (1 for fine), and the
+ * exact n_x a whole-row variant requires (0: any multiple of nxp). */
 int pr_kernel_variant_info(int32_t which, int32_t variant, int32_t *dtype, int32_t *order, int32_t *tile_x,
-                           int32_t *tile_y, int32_t *nxp, int32_t *steps);
+                           int32_t *tile_y, int32_t *nxp, int32_t *steps, int32_t *nx_exact);
 
 /*
  * pr_autotune -- time the fused variants of F (which = 0) or G (which = 1)

@@ -121,11 +121,11 @@ def variants(which):
     """List of dicts describing the fused variants of F (which=0) or G (which=1)."""
     out = []
     for v in range(2, lib().pr_kernel_variant_count(which)):
-        vals = [ctypes.c_int32() for _ in range(6)]
+        vals = [ctypes.c_int32() for _ in range(7)]
         check(lib().pr_kernel_variant_info(which, v, *[ctypes.byref(x) for x in vals]))
         out.append(dict(index=v, name=lib().pr_kernel_variant_name(which, v).decode(), dtype=vals[0].value,
                         order=vals[1].value, tile=(vals[2].value, vals[3].value), nxp=vals[4].value,
-                        steps=vals[5].value))
+                        steps=vals[5].value, nx_exact=vals[6].value))
     return out
 
 

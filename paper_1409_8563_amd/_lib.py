@@ -85,7 +85,7 @@ def lib():
     L.pr_kernel_variant_name.argtypes = [_i32, _i32]
     L.pr_kernel_variant_name.restype = ctypes.c_char_p
     ip = ctypes.POINTER(_i32)
-    L.pr_kernel_variant_info.argtypes = [_i32, _i32, ip, ip, ip, ip, ip, ip]
+    L.pr_kernel_variant_info.argtypes = [_i32, _i32, ip, ip, ip, ip, ip, ip, ip]
     L.pr_autotune_workspace_bytes.argtypes = [pp, _i32, _i32]
     L.pr_autotune_workspace_bytes.restype = _sz
     L.pr_autotune.argtypes = [pp, _i32, _i32, _i32, _vp, _sz, _vp, ip]

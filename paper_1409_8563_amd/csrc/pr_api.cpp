@@ -213,7 +213,8 @@ bool fine_applicable(int v, int dtype, int order, const pr_problem &p)
 {
     if (v == 1) return true;
     const VariantInfo *vi = pr::fine_variant(v);
-    return vi && vi->dtype == dtype && vi->order == order && p.n[0] % vi->nxp == 0;
+    return vi && vi->dtype == dtype && vi->order == order && p.n[0] % vi->nxp == 0 &&
+           (vi->rowx == 0 || p.n[0] == vi->rowx);
 }
 bool coarse_applicable(int v, int dtype, const pr_problem &p)
 {
@@ -228,7 +229,10 @@ int pick_fine_default(const pr_problem &p, int dtype)
     const bool even = p.n[0] % 2 == 0;
     const char *name;
     if (dtype == PR_FP64)
-        name = order == 4 ? (even ? "rk4_f64_o4_t32x16_p2x1" : "rk4_f64_o4_t24x8_p1x1") : "rk4b_f64_t32x32_p1x2_d2";
+        name = order == 4 ? (even ? "rk4_f64_o4_t32x16_p2x1" : "rk4_f64_o4_t24x8_p1x1")
+               : p.n[0] == 128 ? "rk4w_f64_x128_y8_p2x1_w16"
+               : p.n[0] == 64  ? "rk4w_f64_x64_y8_p1x1_w16"
+                               : "rk4b_f64_t32x32_p1x2_d2";
     else
         name = order == 4 ? (even ? "rk4_f32_o4_t32x16_p2x2" : "rk4_f32_o4_t32x16_p1x2")
                           : (even ? "rk4b_f32_t64x32_p2x2_d2" : "rk4b_f32_t32x32_p1x4_d2");
@@ -1249,7 +1253,7 @@ const char *pr_kernel_variant_name(int32_t which, int32_t variant)
 }
 
 int pr_kernel_variant_info(int32_t which, int32_t variant, int32_t *dtype, int32_t *order, int32_t *tile_x,
-                           int32_t *tile_y, int32_t *nxp, int32_t *steps)
+                           int32_t *tile_y, int32_t *nxp, int32_t *steps, int32_t *nx_exact)
 {
     const VariantInfo *vi = which == 0 ? pr::fine_variant(variant) : pr::coarse_variant(variant);
     if (!vi) return fail(PR_EINVAL, "no fused variant %d", variant);
@@ -1259,6 +1263,7 @@ int pr_kernel_variant_info(int32_t which, int32_t variant, int32_t *dtype, int32
     if (tile_y) *tile_y = vi->ty;
     if (nxp) *nxp = vi->nxp;
     if (steps) *steps = vi->steps;
+    if (nx_exact) *nx_exact = vi->rowx;
     return PR_OK;
 }
 

@@ -65,6 +65,7 @@ struct VariantInfo {
     int nxp;              // x points per thread (nx must be a multiple)
     int threads;
     int steps;            // coarse: Euler steps fused per launch
+    int rowx = 0;         // nonzero: whole-row kernel, n_x must equal rowx (= tx, one tile in x)
 };
 int fine_variant_count();
 const VariantInfo *fine_variant(int v);      // v >= 2

@@ -880,6 +880,256 @@ __global__ void __launch_bounds__(BXT *BY)
 }
 
 // ---------------------------------------------------------------------------
+// Fused RK4 step over whole x rows (radius-1 stencils, n_x = 64 * NXP).
+//
+// Lane l of a wavefront holds x = l*NXP .. l*NXP + NXP-1 of NY consecutive
+// rows, so a wavefront covers complete periodic rows: the x neighbours of a
+// point are the lane's own values and, at the ends of its group, the values
+// of lanes l-1 and l+1 (mod 64), moved across the wavefront with DPP
+// rotations (every source lane exists, so the bound control is moot).  No
+// x halo exists and no LDS traffic is spent on x.  In y the
+// block holds EY = NW*NY rows (output TY = EY - 8: a halo of 4 rows per side
+// for the four stages); y neighbours inside a wavefront's rows come from
+// registers, and each wavefront exchanges only its first and last row with
+// its neighbours through LDS.  A wavefront skips a stage once all its rows
+// lie within s rows of the tile edge, where stage s can no longer feed an
+// output point.  z pipeline, prefetch ring and one-barrier LDS double
+// buffering as in rk4_step_fused1b.
+// ---------------------------------------------------------------------------
+constexpr int kDppWaveRor1 = 0x13C;  // lane l receives the value of lane (l - 1) mod 64
+constexpr int kDppWaveRol1 = 0x134;  // lane l receives the value of lane (l + 1) mod 64
+
+template <int CTRL>
+__device__ __forceinline__ float wave_rot(float v)
+{
+    return __builtin_bit_cast(float,
+                              __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v), CTRL, 0xf, 0xf, true));
+}
+template <int CTRL>
+__device__ __forceinline__ double wave_rot(double v)
+{
+    const long long b = __builtin_bit_cast(long long, v);
+    const int lo = __builtin_amdgcn_update_dpp(0, (int)(b & 0xffffffffll), CTRL, 0xf, 0xf, true);
+    const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), CTRL, 0xf, 0xf, true);
+    return __builtin_bit_cast(double, ((long long)hi << 32) | (unsigned int)lo);
+}
+
+template <typename T, int NXP, int NY, int NW, int PD>
+__global__ void __launch_bounds__(64 * NW)
+    rk4_step_rows(const ItemDesc *__restrict__ items, int nitems, int jstep)
+{
+    static_assert(4 % PD == 0, "prefetch depth must divide the unroll");
+    constexpr int R = 1;
+    constexpr int H = 4;
+    constexpr int NX = 64 * NXP;
+    constexpr int EY = NW * NY, TY = EY - 2 * H;
+    constexpr int L = 4;                  // z-ring length (even: LDS slot = phase parity)
+    constexpr int NE = NY == 1 ? 1 : 2;   // exchanged rows per wavefront: first, last
+    static_assert(TY > 0, "tile too small for the halo");
+    __shared__ __align__(16) T lds[4][2][NW][NE][NX];   // [stage input][slot][wavefront][edge][x]
+
+    const int lb = xcd_remap((int)blockIdx.x, (int)gridDim.x);
+    const ItemDesc &it = items[find_item(items, nitems, lb)];
+    if (jstep >= it.nsteps || it.nx != NX) return;
+    const int local = lb - it.block_begin;
+    if (local < 0 || local >= it.nblocks) return;
+
+    const int ny = it.ny, nz = it.nz;
+    const int tyt = local % it.tiles_y;
+    const int zc = local / it.tiles_y;
+    const int y0 = tyt * TY;
+    const int z0 = zc * it.tz;
+    const int zend = min(z0 + it.tz, nz);
+
+    const T *src;
+    T *dst;
+    pingpong<T>(it, jstep, it.nsteps, src, dst);
+
+    const int lane = (int)threadIdx.x & 63;
+    const int wv = __builtin_amdgcn_readfirstlane((int)threadIdx.x >> 6);
+    const int wup = wv > 0 ? wv - 1 : 0;          // clamped: wavefront 0 never uses its upper neighbour
+    const int wdn = wv < NW - 1 ? wv + 1 : NW - 1;
+    const int ry0 = wv * NY;
+    const int cx0 = lane * NXP;
+    int rowoff[NY];
+    bool rowout[NY];
+#pragma unroll
+    for (int iy = 0; iy < NY; ++iy) {
+        const int ry = ry0 + iy;
+        rowoff[iy] = wrapi(y0 - H + ry, ny) * NX + cx0;
+        rowout[iy] = (ry >= H) && (ry < H + TY) && (y0 + ry - H < ny);
+    }
+    const int nxy = NX * ny;
+    // stage s (1..4) can feed an output point only on rows s .. EY-1-s
+    auto wave_active = [&](int s) { return ry0 + NY - 1 >= s && ry0 < EY - s; };
+    const bool act1 = wave_active(1), act2 = wave_active(2), act3 = wave_active(3), act4 = wave_active(4);
+
+    const double dt = it.dt;
+    const double t = (double)(it.step0 + jstep) * dt;
+    const double nu1 = nu_at(it, t);
+    const double nu2 = it.frozen ? nu1 : nu_at(it, t + 0.5 * dt);
+    const double nu4 = it.frozen ? nu1 : nu_at(it, t + dt);
+    const Wts<T, R> w1 = uni(fine_weights<T, R>(it, nu1));
+    const Wts<T, R> w2 = uni(fine_weights<T, R>(it, nu2));
+    const Wts<T, R> w4 = uni(fine_weights<T, R>(it, nu4));
+    RK4Consts<T> kc = rk4_consts<T>(dt);
+    kc.c1 = uni(kc.c1);
+    kc.c2 = uni(kc.c2);
+    kc.c3 = uni(kc.c3);
+    kc.b1 = uni(kc.b1);
+    kc.b2 = uni(kc.b2);
+    kc.b3 = uni(kc.b3);
+    kc.b4 = uni(kc.b4);
+
+    T ur[L][NY][NXP], y1[L][NY][NXP], y2[L][NY][NXP], y3[L][NY][NXP], ac[L][NY][NXP];
+    T pf[PD][NY][NXP];
+
+    auto load_plane = [&](int p, T(&dstp)[NY][NXP]) {
+        const T *base = src + (size_t)wrapi(p, nz) * nxy;
+#pragma unroll
+        for (int iy = 0; iy < NY; ++iy) {
+            const Vec<T, NXP> v = gld<Vec<T, NXP>>(base + rowoff[iy]);
+#pragma unroll
+            for (int ix = 0; ix < NXP; ++ix) dstp[iy][ix] = v.v[ix];
+        }
+    };
+
+    // first and last row of this wavefront's values of a plane -> LDS
+    auto put = [&](auto Bc, auto SLc, const T(&v)[NY][NXP]) {
+        constexpr int B = decltype(Bc)::value;
+        constexpr int SL = decltype(SLc)::value;
+        Vec<T, NXP> a;
+#pragma unroll
+        for (int ix = 0; ix < NXP; ++ix) a.v[ix] = v[0][ix];
+        *reinterpret_cast<Vec<T, NXP> *>(&lds[B][SL][wv][0][cx0]) = a;
+        if constexpr (NE == 2) {
+            Vec<T, NXP> b;
+#pragma unroll
+            for (int ix = 0; ix < NXP; ++ix) b.v[ix] = v[NY - 1][ix];
+            *reinterpret_cast<Vec<T, NXP> *>(&lds[B][SL][wv][1][cx0]) = b;
+        }
+    };
+
+    // rows above and below this wavefront of a plane of stage input B, slot SL
+    struct Nb {
+        Vec<T, NXP> up, dn;
+    };
+    auto fetch = [&](auto Bc, auto SLc) {
+        constexpr int B = decltype(Bc)::value;
+        constexpr int SL = decltype(SLc)::value;
+        Nb nb;
+        nb.up = *reinterpret_cast<const Vec<T, NXP> *>(&lds[B][SL][wup][NE - 1][cx0]);
+        nb.dn = *reinterpret_cast<const Vec<T, NXP> *>(&lds[B][SL][wdn][0][cx0]);
+        return nb;
+    };
+
+    // S = L(f)(plane q) on this wavefront's rows.  Centre and z neighbours
+    // from the ring `in` (slots SC, SCM = plane q-1, SCP = plane q+1); the
+    // rows above and below the wavefront from `nb`.
+    auto stencil = [&](const Nb &nb, const T(&in)[L][NY][NXP], auto SCc, auto SCMc, auto SCPc, const Wts<T, R> &w,
+                       T(&S)[NY][NXP]) {
+        constexpr int SC = decltype(SCc)::value;
+        constexpr int SCM = decltype(SCMc)::value;
+        constexpr int SCP = decltype(SCPc)::value;
+#pragma unroll
+        for (int iy = 0; iy < NY; ++iy) {
+            const T left = wave_rot<kDppWaveRor1>(in[SC][iy][NXP - 1]);
+            const T right = wave_rot<kDppWaveRol1>(in[SC][iy][0]);
+#pragma unroll
+            for (int ix = 0; ix < NXP; ++ix) {
+                T mn[3][1], pn[3][1];
+                mn[0][0] = (ix >= 1) ? in[SC][iy][ix - 1] : left;
+                pn[0][0] = (ix + 1 < NXP) ? in[SC][iy][ix + 1] : right;
+                mn[1][0] = (iy >= 1) ? in[SC][iy - 1][ix] : nb.up.v[ix];
+                pn[1][0] = (iy + 1 < NY) ? in[SC][iy + 1][ix] : nb.dn.v[ix];
+                mn[2][0] = in[SCM][iy][ix];
+                pn[2][0] = in[SCP][iy][ix];
+                S[iy][ix] = apply<T, 1>(w, in[SC][iy][ix], mn, pn);
+            }
+        }
+    };
+
+    auto body = [&](auto Mc, int p) {
+        constexpr int M = decltype(Mc)::value;
+        constexpr int WS = M & 1;        // slot written in this iteration
+        constexpr int RS = (M + 1) & 1;  // slot written in the previous iteration
+        __syncthreads();
+#pragma unroll
+        for (int iy = 0; iy < NY; ++iy)
+#pragma unroll
+            for (int ix = 0; ix < NXP; ++ix) ur[slot<L>(M, 0)][iy][ix] = pf[M % PD][iy][ix];
+        load_plane(p + PD, pf[M % PD]);
+        put(ic<0>{}, ic<WS>{}, ur[slot<L>(M, 0)]);
+
+        T S[NY][NXP];
+        // stage 1 at plane p - 1
+        if (act1 && p >= z0 - 2) {
+            stencil(fetch(ic<0>{}, ic<RS>{}), ur, ic<slot<L>(M, 1)>{}, ic<slot<L>(M, 2)>{}, ic<slot<L>(M, 0)>{}, w1, S);
+#pragma unroll
+            for (int iy = 0; iy < NY; ++iy)
+#pragma unroll
+                for (int ix = 0; ix < NXP; ++ix) {
+                    const T u = ur[slot<L>(M, 1)][iy][ix];
+                    y1[slot<L>(M, 1)][iy][ix] = fmaT(kc.c1, S[iy][ix], u);
+                    ac[slot<L>(M, 1)][iy][ix] = fmaT(kc.b1, S[iy][ix], u);
+                }
+            put(ic<1>{}, ic<WS>{}, y1[slot<L>(M, 1)]);
+        }
+        // stage 2 at plane p - 2
+        if (act2 && p >= z0) {
+            stencil(fetch(ic<1>{}, ic<RS>{}), y1, ic<slot<L>(M, 2)>{}, ic<slot<L>(M, 3)>{}, ic<slot<L>(M, 1)>{}, w2, S);
+#pragma unroll
+            for (int iy = 0; iy < NY; ++iy)
+#pragma unroll
+                for (int ix = 0; ix < NXP; ++ix) {
+                    const T u = ur[slot<L>(M, 2)][iy][ix];
+                    y2[slot<L>(M, 2)][iy][ix] = fmaT(kc.c2, S[iy][ix], u);
+                    ac[slot<L>(M, 2)][iy][ix] = fmaT(kc.b2, S[iy][ix], ac[slot<L>(M, 2)][iy][ix]);
+                }
+            put(ic<2>{}, ic<WS>{}, y2[slot<L>(M, 2)]);
+        }
+        // stage 3 at plane p - 3
+        if (act3 && p >= z0 + 2) {
+            stencil(fetch(ic<2>{}, ic<RS>{}), y2, ic<slot<L>(M, 3)>{}, ic<slot<L>(M, 4)>{}, ic<slot<L>(M, 2)>{}, w2, S);
+#pragma unroll
+            for (int iy = 0; iy < NY; ++iy)
+#pragma unroll
+                for (int ix = 0; ix < NXP; ++ix) {
+                    const T u = ur[slot<L>(M, 3)][iy][ix];
+                    y3[slot<L>(M, 3)][iy][ix] = fmaT(kc.c3, S[iy][ix], u);
+                    ac[slot<L>(M, 3)][iy][ix] = fmaT(kc.b3, S[iy][ix], ac[slot<L>(M, 3)][iy][ix]);
+                }
+            put(ic<3>{}, ic<WS>{}, y3[slot<L>(M, 3)]);
+        }
+        // stage 4 at plane p - 4, stored
+        const int q = p - 4;
+        if (act4 && p >= z0 + 4 && q < zend) {
+            stencil(fetch(ic<3>{}, ic<RS>{}), y3, ic<slot<L>(M, 4)>{}, ic<slot<L>(M, 5)>{}, ic<slot<L>(M, 3)>{}, w4, S);
+            T *obase = dst + (size_t)q * nxy;
+#pragma unroll
+            for (int iy = 0; iy < NY; ++iy) {
+                if (rowout[iy]) {
+                    Vec<T, NXP> v;
+#pragma unroll
+                    for (int ix = 0; ix < NXP; ++ix)
+                        v.v[ix] = fmaT(kc.b4, S[iy][ix], ac[slot<L>(M, 4)][iy][ix]);
+                    gst<Vec<T, NXP>>(obase + rowoff[iy], v);
+                }
+            }
+        }
+    };
+
+    const int pstart = z0 - 4;
+    const int niter = (zend - z0) + 8;
+#pragma unroll
+    for (int d = 0; d < PD; ++d) load_plane(pstart + d, pf[d]);
+    for (int pb = 0; pb < niter; pb += L) {
+        [&]<int... Ms>(std::integer_sequence<int, Ms...>) {
+            (body(ic<Ms>{}, pstart + pb + Ms), ...);
+        }(std::make_integer_sequence<int, L>{});
+    }
+}
+// ---------------------------------------------------------------------------
 // Fused forward Euler chunk with one barrier per z plane (same scheme as
 // rk4_step_fused1b: stage outputs go to LDS and are read one iteration later).
 // ---------------------------------------------------------------------------
@@ -1542,6 +1792,15 @@ void coarse_launch_1c(const ItemDesc *items, int nitems, int nblocks, int chunk,
 #define COARSE_1C(T, DT, S, NXP, NY, BXT, BY, PD, NAME)                                                   \
     CoarseEntry{VariantInfo{NAME, DT, 0, BXT * NXP - 2 * S, BY * NY - 2 * S, NXP, BXT * BY, S},          \
                 &coarse_launch_1c<T, S, NXP, NY, BXT, BY, PD>}
+template <typename T, int NXP, int NY, int NW, int PD>
+void fine_launch_rows(const ItemDesc *items, int nitems, int nblocks, int jstep, hipStream_t s)
+{
+    hipLaunchKernelGGL((rk4_step_rows<T, NXP, NY, NW, PD>), dim3(nblocks), dim3(64 * NW), 0, s, items, nitems,
+                       jstep);
+}
+#define FINE_ROWS(T, DT, NXP, NY, NW, PD, NAME)                                                          \
+    FineEntry{VariantInfo{NAME, DT, 2, 64 * NXP, NW * NY - 8, NXP, 64 * NW, 1, 64 * NXP},              \
+              &fine_launch_rows<T, NXP, NY, NW, PD>}
 #define FINE_1C(T, DT, NXP, NY, BXT, BY, PD, PAD, NAME)                                                  \
     FineEntry{VariantInfo{NAME, DT, 2, BXT * NXP - 8, BY * NY - 8, NXP, BXT * BY, 1},                  \
               &fine_launch_1c<T, NXP, NY, BXT, BY, PD, PAD>}
@@ -1592,6 +1851,16 @@ const FineEntry kFine[] = {
     FINE_1C(float, 1, 2, 2, 36, 20, 2, 0, "rk4c_f32_t64x32_p2x2_pad0"),
     FINE_1C(float, 1, 4, 2, 18, 20, 2, 4, "rk4c_f32_t64x32_p4x2_pad4"),
     FINE_1C(float, 1, 2, 4, 36, 10, 2, 4, "rk4c_f32_t64x32_p2x4_pad4"),
+    FINE_ROWS(double, 2, 2, 1, 16, 2, "rk4w_f64_x128_y8_p2x1_w16"),
+    FINE_ROWS(double, 2, 2, 1, 16, 1, "rk4w_f64_x128_y8_p2x1_w16_d1"),
+    FINE_ROWS(double, 2, 2, 2, 8, 2, "rk4w_f64_x128_y8_p2x2_w8"),
+    FINE_ROWS(double, 2, 1, 1, 16, 2, "rk4w_f64_x64_y8_p1x1_w16"),
+    FINE_ROWS(double, 2, 1, 2, 8, 2, "rk4w_f64_x64_y8_p1x2_w8"),
+    FINE_ROWS(double, 2, 1, 3, 8, 2, "rk4w_f64_x64_y16_p1x3_w8"),
+    FINE_ROWS(float, 1, 4, 2, 8, 2, "rk4w_f32_x256_y8_p4x2_w8"),
+    FINE_ROWS(float, 1, 2, 1, 16, 2, "rk4w_f32_x128_y8_p2x1_w16"),
+    FINE_ROWS(float, 1, 2, 2, 8, 2, "rk4w_f32_x128_y8_p2x2_w8"),
+    FINE_ROWS(float, 1, 2, 3, 8, 2, "rk4w_f32_x128_y16_p2x3_w8"),
 };
 
 const CoarseEntry kCoarse[] = {

@@ -179,8 +179,32 @@ def test_variant_registry():
     for v in fine:
         assert v["dtype"] in (1, 2) and v["order"] in (2, 4) and v["steps"] == 1
         assert v["tile"][0] > 0 and v["tile"][1] > 0
+        if v["nx_exact"]:
+            # whole-row kernels: one lane per nxp consecutive x of a 64-lane wavefront
+            assert v["nx_exact"] == 64 * v["nxp"] == v["tile"][0]
+    assert any(v["nx_exact"] for v in fine)
     for v in coarse:
         assert v["order"] == 0 and v["steps"] >= 1
     assert L.lib().pr_kernel_variant_name(0, 1) == b"rk4_unfused_reference"
     assert L.lib().pr_set_kernel_variant(10 ** 6, 0) == L.PR_EINVAL
     assert L.lib().pr_set_kernel_variant(0, 0) == 0
+
+
+def test_whole_row_variant_rejects_other_nx():
+    """A forced whole-row variant on a grid whose n_x it does not cover is
+    refused before any launch."""
+    import ctypes
+    import paper_1409_8563_amd as pr
+    import workloads as W
+    L = _lib()
+    row = [v for v in pr.variants(0) if v["nx_exact"] == 128 and v["dtype"] == 2][0]
+    p = W.small_problem(n=(64, 40, 20), P=2, nf=4)
+    p.flags |= W.ALLOW_UNSTABLE
+    s = L.to_struct(p)
+    steps = (ctypes.c_int64 * 1)(0)
+    try:
+        assert L.lib().pr_set_kernel_variant(row["index"], 0) == 0
+        rc = L.lib().pr_fine_sweep(ctypes.byref(s), 2, 1, 16, 16 + (1 << 30), steps, 1, 16, 1 << 40, None)
+    finally:
+        L.lib().pr_set_kernel_variant(0, 0)
+    assert rc == L.PR_EUNSUPPORTED

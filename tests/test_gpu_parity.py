@@ -103,7 +103,8 @@ def test_fp32_sweeps_against_fp64_oracle(pr, orc):
 def _applicable(pr, which, dtype, order, nx):
     out = [1]
     for v in pr.variants(which):
-        if v["dtype"] == dtype and (which == 1 or v["order"] == order) and nx % v["nxp"] == 0:
+        if v["dtype"] == dtype and (which == 1 or v["order"] == order) and nx % v["nxp"] == 0 \
+                and v.get("nx_exact", 0) in (0, nx):
             out.append(v["index"])
     return out
 
@@ -129,6 +130,34 @@ def test_fine_variants_bitwise_identical(pr, dtype, order):
     assert len(outs) >= 2
     for v, o in outs.items():
         assert torch.equal(o, base), v
+
+
+@pytest.mark.parametrize("dtype", [1, 2])
+@pytest.mark.parametrize("n3", [(128, 52, 21), (64, 37, 19), (256, 20, 9), (128, 8, 5)])
+def test_fine_whole_row_variants_bitwise_identical(pr, dtype, n3):
+    """The whole-row kernels (x neighbours across the wavefront) agree bit for
+    bit with the unfused reference and the tiled kernels, on grids with a
+    ragged last y tile, fewer rows than one tile and z shorter than the
+    pipeline."""
+    import torch
+    tdt = torch.float64 if dtype == 2 else torch.float32
+    p = W.small_problem(n=n3, a=(0.7, -0.45, 0.3), nu0=0.002, P=2, nf=64)
+    u = cuda(W.random_field(p.n, 141), tdt)
+    vs = _applicable(pr, 0, dtype, 2, p.n[0])
+    rows = [v["index"] for v in pr.variants(0) if v["nx_exact"] == p.n[0] and v["dtype"] == dtype]
+    if not rows:
+        pytest.skip("no whole-row variant for n_x=%d" % p.n[0])
+    outs = {}
+    try:
+        for v in vs:
+            say("fine variant", v, dtype, n3)
+            pr.set_kernel_variant(v, 0)
+            outs[v] = pr.fine_sweep(p, u, 3, 3)
+    finally:
+        pr.set_kernel_variant(0, 0)
+    assert set(rows) <= set(outs)
+    for v, o in outs.items():
+        assert torch.equal(o, outs[1]), v
 
 
 @pytest.mark.parametrize("dtype", [1, 2])
