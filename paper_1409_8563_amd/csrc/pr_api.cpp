@@ -220,7 +220,7 @@ bool coarse_applicable(int v, int dtype, const pr_problem &p)
 {
     if (v == 1) return true;
     const VariantInfo *vi = pr::coarse_variant(v);
-    return vi && vi->dtype == dtype && p.n[0] % vi->nxp == 0;
+    return vi && vi->dtype == dtype && p.n[0] % vi->nxp == 0 && (vi->rowx == 0 || p.n[0] == vi->rowx);
 }
 
 int pick_fine_default(const pr_problem &p, int dtype)
@@ -253,8 +253,18 @@ int pick_fine(const pr_problem &p, int dtype)
 int pick_coarse_default(const pr_problem &p, int dtype)
 {
     const bool even = p.n[0] % 2 == 0;
-    const char *name = dtype == PR_FP64 ? (even ? "euler4b_f64_t32x32_p2x2_d2" : "euler4b_f64_t32x32_p1x4_d2")
-                                        : (even ? "euler4b_f32_t32x32_p2x2_d2" : "euler4b_f32_t32x32_p1x4_d2");
+    const int nx = p.n[0];
+    const char *name;
+    if (dtype == PR_FP64)
+        name = nx == 128 ? "euler4w_f64_x128_y8_p2x1_w16"
+               : nx == 64 ? "euler4w_f64_x64_y8_p1x1_w16"
+               : even     ? "euler4b_f64_t32x32_p2x2_d2"
+                          : "euler4b_f64_t32x32_p1x4_d2";
+    else
+        name = nx == 256 ? "euler4w_f32_x256_y8_p4x1_w16"
+               : nx == 128 ? "euler4w_f32_x128_y8_p2x1_w16"
+               : even      ? "euler4b_f32_t32x32_p2x2_d2"
+                           : "euler4b_f32_t32x32_p1x4_d2";
     return find_coarse(name);
 }
 
@@ -1000,17 +1010,14 @@ int pr_plan_create(const pr_problem *probs, int32_t ninst, int32_t mode, void *w
             return fail(PR_EUNSUPPORTED, "instances of one plan must share fine_order");
         }
     }
-    if (!fok) {
-        // fall back to the layout with one x point per thread (any n_x)
-        pr_problem odd = probs[0];
-        odd.n[0] = 3;
-        fv = g_fine_forced ? -1 : pick_fine_default(odd, pl->dtype);
-    }
-    if (!cok) {
-        pr_problem odd = probs[0];
-        odd.n[0] = 3;
-        cv = g_coarse_forced ? -1 : pick_coarse_default(odd, pl->dtype);
-    }
+    // fallback: the tiled default for a generic n_x, even if every instance
+    // has an even n_x (two x points per thread), else odd (one per thread)
+    bool all_even = true;
+    for (int i = 0; i < ninst; ++i) all_even = all_even && probs[i].n[0] % 2 == 0;
+    pr_problem generic = probs[0];
+    generic.n[0] = all_even ? 2 : 3;
+    if (!fok) fv = g_fine_forced ? -1 : pick_fine_default(generic, pl->dtype);
+    if (!cok) cv = g_coarse_forced ? -1 : pick_coarse_default(generic, pl->dtype);
     if (fv < 1 || cv < 1) {
         delete pl;
         return fail(PR_EUNSUPPORTED, "forced kernel variant does not apply to every instance");

@@ -1298,6 +1298,174 @@ __global__ void __launch_bounds__(BXT *BY)
 }
 
 // ---------------------------------------------------------------------------
+// S fused Euler steps of G over whole x rows (n_x = 64 * NXP): the layout of
+// rk4_step_rows (x neighbours by wavefront rotation, y-edge rows through
+// LDS, y halo of S rows per side, stages skipped per wavefront near the tile
+// edge) with the z pipeline of euler_chunk_fused1b.
+// ---------------------------------------------------------------------------
+template <typename T, int S, int NXP, int NY, int NW, int PD>
+__global__ void __launch_bounds__(64 * NW)
+    euler_chunk_rows(const ItemDesc *__restrict__ items, int nitems, int chunk)
+{
+    static_assert(6 % PD == 0, "prefetch depth must divide the unroll");
+    constexpr int H = S;
+    constexpr int NX = 64 * NXP;
+    constexpr int EY = NW * NY, TY = EY - 2 * H;
+    constexpr int L = 3;                  // z-ring length
+    constexpr int U = 6;                  // unroll: ring phase and LDS slot parity
+    constexpr int NE = NY == 1 ? 1 : 2;   // exchanged rows per wavefront: first, last
+    static_assert(TY > 0, "tile too small for the halo");
+    __shared__ __align__(16) T lds[S][2][NW][NE][NX];   // [stage input][slot][wavefront][edge][x]
+
+    const int lb = xcd_remap((int)blockIdx.x, (int)gridDim.x);
+    const ItemDesc &it = items[find_item(items, nitems, lb)];
+    const int nchunks = (it.nsteps + S - 1) / S;
+    if (chunk >= nchunks || it.nx != NX) return;
+    const int local = lb - it.block_begin;
+    if (local < 0 || local >= it.nblocks) return;
+
+    const int ny = it.ny, nz = it.nz;
+    const int tyt = local % it.tiles_y;
+    const int zc = local / it.tiles_y;
+    const int y0 = tyt * TY;
+    const int z0 = zc * it.tz;
+    const int zend = min(z0 + it.tz, nz);
+
+    const T *src;
+    T *dst;
+    pingpong<T>(it, chunk, nchunks, src, dst);
+
+    const int lane = (int)threadIdx.x & 63;
+    const int wv = __builtin_amdgcn_readfirstlane((int)threadIdx.x >> 6);
+    const int wup = wv > 0 ? wv - 1 : 0;
+    const int wdn = wv < NW - 1 ? wv + 1 : NW - 1;
+    const int ry0 = wv * NY;
+    const int cx0 = lane * NXP;
+    int rowoff[NY];
+    bool rowout[NY];
+#pragma unroll
+    for (int iy = 0; iy < NY; ++iy) {
+        const int ry = ry0 + iy;
+        rowoff[iy] = wrapi(y0 - H + ry, ny) * NX + cx0;
+        rowout[iy] = (ry >= H) && (ry < H + TY) && (y0 + ry - H < ny);
+    }
+    const int nxy = NX * ny;
+
+    Wts<T, 1> w[S];
+    T dts[S];
+#pragma unroll
+    for (int s = 0; s < S; ++s) {
+        const int64_t j = (int64_t)chunk * S + s;
+        const bool act = j < it.nsteps;
+        const double nu = nu_at(it, (double)(it.step0 + j) * it.dt);
+        w[s] = uni(coarse_weights<T>(it, nu));
+        dts[s] = uni(act ? (T)it.dt : (T)0);
+    }
+
+    T f[S][L][NY][NXP];
+    T pf[PD][NY][NXP];
+
+    auto load_plane = [&](int p, T(&dstp)[NY][NXP]) {
+        const T *base = src + (size_t)wrapi(p, nz) * nxy;
+#pragma unroll
+        for (int iy = 0; iy < NY; ++iy) {
+            const Vec<T, NXP> v = gld<Vec<T, NXP>>(base + rowoff[iy]);
+#pragma unroll
+            for (int ix = 0; ix < NXP; ++ix) dstp[iy][ix] = v.v[ix];
+        }
+    };
+
+    auto put = [&](auto Bc, auto SLc, const T(&v)[NY][NXP]) {
+        constexpr int B = decltype(Bc)::value;
+        constexpr int SL = decltype(SLc)::value;
+        Vec<T, NXP> a;
+#pragma unroll
+        for (int ix = 0; ix < NXP; ++ix) a.v[ix] = v[0][ix];
+        *reinterpret_cast<Vec<T, NXP> *>(&lds[B][SL][wv][0][cx0]) = a;
+        if constexpr (NE == 2) {
+            Vec<T, NXP> b;
+#pragma unroll
+            for (int ix = 0; ix < NXP; ++ix) b.v[ix] = v[NY - 1][ix];
+            *reinterpret_cast<Vec<T, NXP> *>(&lds[B][SL][wv][1][cx0]) = b;
+        }
+    };
+
+    auto body = [&](auto Mc, int p) {
+        constexpr int M = decltype(Mc)::value;
+        constexpr int WS = M & 1, RS = (M + 1) & 1;
+        __syncthreads();
+#pragma unroll
+        for (int iy = 0; iy < NY; ++iy)
+#pragma unroll
+            for (int ix = 0; ix < NXP; ++ix) f[0][slot<L>(M, 0)][iy][ix] = pf[M % PD][iy][ix];
+        put(ic<0>{}, ic<WS>{}, f[0][slot<L>(M, 0)]);
+        load_plane(p + PD, pf[M % PD]);
+
+        [&]<int... Ss>(std::integer_sequence<int, Ss...>) {
+            (
+                [&] {
+                    constexpr int s = Ss + 1;          // stage s computes plane p - s from f[s-1]
+                    constexpr int sc = slot<L>(M, s);
+                    const bool wact = ry0 + NY - 1 >= s && ry0 < EY - s;
+                    if (wact && p >= z0 - S + 2 * s && p < zend + S) {
+                        const Vec<T, NXP> up =
+                            *reinterpret_cast<const Vec<T, NXP> *>(&lds[s - 1][RS][wup][NE - 1][cx0]);
+                        const Vec<T, NXP> dn = *reinterpret_cast<const Vec<T, NXP> *>(&lds[s - 1][RS][wdn][0][cx0]);
+                        T res[NY][NXP];
+#pragma unroll
+                        for (int iy = 0; iy < NY; ++iy) {
+                            const T left = wave_rot<kDppWaveRor1>(f[s - 1][sc][iy][NXP - 1]);
+                            const T right = wave_rot<kDppWaveRol1>(f[s - 1][sc][iy][0]);
+#pragma unroll
+                            for (int ix = 0; ix < NXP; ++ix) {
+                                T mn[3][1], pn[3][1];
+                                mn[0][0] = (ix >= 1) ? f[s - 1][sc][iy][ix - 1] : left;
+                                pn[0][0] = (ix + 1 < NXP) ? f[s - 1][sc][iy][ix + 1] : right;
+                                mn[1][0] = (iy >= 1) ? f[s - 1][sc][iy - 1][ix] : up.v[ix];
+                                pn[1][0] = (iy + 1 < NY) ? f[s - 1][sc][iy + 1][ix] : dn.v[ix];
+                                mn[2][0] = f[s - 1][slot<L>(M, s + 1)][iy][ix];
+                                pn[2][0] = f[s - 1][slot<L>(M, s - 1)][iy][ix];
+                                const T cen = f[s - 1][sc][iy][ix];
+                                const T Sv = apply<T, 1>(w[s - 1], cen, mn, pn);
+                                res[iy][ix] = fmaT(dts[s - 1], Sv, cen);
+                            }
+                        }
+                        if constexpr (s < S) {
+#pragma unroll
+                            for (int iy = 0; iy < NY; ++iy)
+#pragma unroll
+                                for (int ix = 0; ix < NXP; ++ix) f[s][slot<L>(M, s)][iy][ix] = res[iy][ix];
+                            put(ic<s>{}, ic<WS>{}, res);
+                        } else {
+                            T *obase = dst + (size_t)(p - S) * nxy;
+#pragma unroll
+                            for (int iy = 0; iy < NY; ++iy) {
+                                if (rowout[iy]) {
+                                    Vec<T, NXP> v;
+#pragma unroll
+                                    for (int ix = 0; ix < NXP; ++ix) v.v[ix] = res[iy][ix];
+                                    gst<Vec<T, NXP>>(obase + rowoff[iy], v);
+                                }
+                            }
+                        }
+                    }
+                }(),
+                ...);
+        }(std::make_integer_sequence<int, S>{});
+    };
+
+    const int pstart = z0 - S;
+    const int niter = (zend - z0) + 2 * S;
+#pragma unroll
+    for (int d = 0; d < PD; ++d) load_plane(pstart + d, pf[d]);
+    for (int pb = 0; pb < niter; pb += U) {
+        [&]<int... Ms>(std::integer_sequence<int, Ms...>) {
+            (body(ic<Ms>{}, pstart + pb + Ms), ...);
+        }(std::make_integer_sequence<int, U>{});
+    }
+}
+
+// ---------------------------------------------------------------------------
 template <typename T, int S, int NXP, int NY, int BXT, int BY, int PD>
 __global__ void __launch_bounds__(BXT *BY)
     euler_chunk_fused1c(const ItemDesc *__restrict__ items, int nitems, int chunk)
@@ -1804,6 +1972,15 @@ void fine_launch_rows(const ItemDesc *items, int nitems, int nblocks, int jstep,
 #define FINE_1C(T, DT, NXP, NY, BXT, BY, PD, PAD, NAME)                                                  \
     FineEntry{VariantInfo{NAME, DT, 2, BXT * NXP - 8, BY * NY - 8, NXP, BXT * BY, 1},                  \
               &fine_launch_1c<T, NXP, NY, BXT, BY, PD, PAD>}
+template <typename T, int S, int NXP, int NY, int NW, int PD>
+void coarse_launch_rows(const ItemDesc *items, int nitems, int nblocks, int chunk, hipStream_t s)
+{
+    hipLaunchKernelGGL((euler_chunk_rows<T, S, NXP, NY, NW, PD>), dim3(nblocks), dim3(64 * NW), 0, s, items, nitems,
+                       chunk);
+}
+#define COARSE_ROWS(T, DT, S, NXP, NY, NW, PD, NAME)                                                     \
+    CoarseEntry{VariantInfo{NAME, DT, 0, 64 * NXP, NW * NY - 2 * S, NXP, 64 * NW, S, 64 * NXP},         \
+                &coarse_launch_rows<T, S, NXP, NY, NW, PD>}
 #define COARSE_1B(T, DT, S, NXP, NY, BXT, BY, PD, NAME)                                                   \
     CoarseEntry{VariantInfo{NAME, DT, 0, BXT * NXP - 2 * S, BY * NY - 2 * S, NXP, BXT * BY, S},          \
                 &coarse_launch_1b<T, S, NXP, NY, BXT, BY, PD>}
@@ -1885,6 +2062,13 @@ const CoarseEntry kCoarse[] = {
     COARSE_1C(double, 2, 2, 2, 2, 18, 18, 2, "euler2c_f64_t32x32_p2x2"),
     COARSE_1C(float, 1, 4, 2, 2, 20, 20, 2, "euler4c_f32_t32x32_p2x2"),
     COARSE_1C(float, 1, 2, 2, 2, 18, 18, 2, "euler2c_f32_t32x32_p2x2"),
+    COARSE_ROWS(double, 2, 4, 2, 1, 16, 2, "euler4w_f64_x128_y8_p2x1_w16"),
+    COARSE_ROWS(double, 2, 2, 2, 1, 16, 2, "euler2w_f64_x128_y12_p2x1_w16"),
+    COARSE_ROWS(double, 2, 4, 2, 2, 8, 2, "euler4w_f64_x128_y8_p2x2_w8"),
+    COARSE_ROWS(double, 2, 4, 1, 1, 16, 2, "euler4w_f64_x64_y8_p1x1_w16"),
+    COARSE_ROWS(float, 1, 4, 4, 1, 16, 2, "euler4w_f32_x256_y8_p4x1_w16"),
+    COARSE_ROWS(float, 1, 4, 4, 2, 8, 2, "euler4w_f32_x256_y8_p4x2_w8"),
+    COARSE_ROWS(float, 1, 4, 2, 1, 16, 2, "euler4w_f32_x128_y8_p2x1_w16"),
 };
 
 constexpr int kNumFine = (int)(sizeof(kFine) / sizeof(kFine[0]));

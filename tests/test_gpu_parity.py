@@ -180,6 +180,32 @@ def test_coarse_variants_bitwise_identical(pr, dtype):
 
 
 @pytest.mark.parametrize("dtype", [1, 2])
+@pytest.mark.parametrize("n3", [(128, 44, 19), (64, 21, 11), (256, 12, 7)])
+def test_coarse_whole_row_variants_bitwise_identical(pr, dtype, n3):
+    """Whole-row Euler chunks agree bit for bit with the reference and the
+    tiled chunks, including a step count that leaves a partial chunk."""
+    import torch
+    tdt = torch.float64 if dtype == 2 else torch.float32
+    p = W.small_problem(n=n3, a=(0.7, -0.45, 0.0), nu0=0.002, P=1, nc=13)
+    p.flags |= W.ALLOW_UNSTABLE    # 13 steps of a random field: only the bits are compared
+    u = cuda(W.random_field(p.n, 151), tdt)
+    rows = [v["index"] for v in pr.variants(1) if v["nx_exact"] == p.n[0] and v["dtype"] == dtype]
+    if not rows:
+        pytest.skip("no whole-row variant for n_x=%d" % p.n[0])
+    outs = {}
+    try:
+        for v in _applicable(pr, 1, dtype, 0, p.n[0]):
+            say("coarse variant", v, dtype, n3)
+            pr.set_kernel_variant(0, v)
+            outs[v] = pr.coarse_sweep(p, u, 2, 13)
+    finally:
+        pr.set_kernel_variant(0, 0)
+    assert set(rows) <= set(outs)
+    for v, o in outs.items():
+        assert torch.equal(o, outs[1]), v
+
+
+@pytest.mark.parametrize("dtype", [1, 2])
 def test_translation_equivariance_bitwise(pr, dtype):
     import torch
     say("translation", dtype)
