@@ -153,18 +153,29 @@ def main():
     extra = {}
     if not args.no_compare:
         # time-to-solution comparisons (outside the timed region)
-        def timed(fn, reps=2):
-            fn()
-            torch.cuda.synchronize()
-            t = time.perf_counter()
-            for _ in range(reps):
+        def timed(fn, reps=10, warm=3):
+            """median wall time (ms) of reps calls after warm calls"""
+            for _ in range(warm):
                 fn()
             torch.cuda.synchronize()
-            return (time.perf_counter() - t) * 1e3 / reps
+            ts = []
+            for _ in range(reps):
+                t = time.perf_counter()
+                fn()
+                torch.cuda.synchronize()
+                ts.append((time.perf_counter() - t) * 1e3)
+            return float(np.median(ts))
 
         u64 = u0
         out64 = torch.empty_like(u64)
         t_batched = timed(lambda: plan.solve([u0], uT=[uT], want_log=False))
+        plan_g = pr.Plan([p], mode | pr.PR_MODE_GRAPH)
+        t0g = time.perf_counter()
+        plan_g.solve([u0], uT=[uT], want_log=False)
+        torch.cuda.synchronize()
+        t_capture = (time.perf_counter() - t0g) * 1e3
+        t_graph = timed(lambda: plan_g.solve([u0], uT=[uT], want_log=False))
+        del plan_g
         plan_ps = pr.Plan([p], pr.PR_MODE_FP64 | pr.PR_MODE_PER_SLICE)
         t_plain = timed(lambda: plan_ps.solve([u0], uT=[uT], want_log=False))
         del plan_ps
@@ -173,11 +184,13 @@ def main():
         plan_sk = pr.Plan([q], mode)
         t_skip = timed(lambda: plan_sk.solve([u0], uT=[uT], want_log=False))
         del plan_sk
-        t_serial = timed(lambda: pr.fine_sweep(p, u64, 0, p.nt_fine, u_out=out64))
-        t_coarse = timed(lambda: pr.coarse_sweep(p, u64, 0, p.nt_coarse, u_out=out64))
+        t_serial = timed(lambda: pr.fine_sweep(p, u64, 0, p.nt_fine, u_out=out64), reps=5, warm=1)
+        t_coarse = timed(lambda: pr.coarse_sweep(p, u64, 0, p.nt_coarse, u_out=out64), reps=5, warm=1)
         tau = (t_coarse / p.nt_coarse) / (t_serial / p.nt_fine)
         extra = {
             "time_to_solution_ms": {"parareal_batched": round(t_batched, 3),
+                                    "parareal_batched_graph_replay": round(t_graph, 3),
+                                    "first_call_with_graph_capture": round(t_capture, 3),
                                     "parareal_batched_skip_converged": round(t_skip, 3),
                                     "parareal_plain_fp64_per_slice": round(t_plain, 3),
                                     "serial_fine_fp64": round(t_serial, 3)},
@@ -203,11 +216,11 @@ def main():
                 return {"max_abs": float("%.3e" % o[0]), "rel_l2": float("%.3e" % np.sqrt(o[2] / o[3]))}
 
             plan_m = pr.Plan([pm], pr.PR_MODE_MIXED)
-            t_m = timed(lambda: plan_m.solve([um], uT=[uT_mixed], want_log=False), reps=1)
+            t_m = timed(lambda: plan_m.solve([um], uT=[uT_mixed], want_log=False), reps=3, warm=1)
             del plan_m
             torch.cuda.empty_cache()
             plan_p = pr.Plan([pm], pr.PR_MODE_FP64 | pr.PR_MODE_PER_SLICE)
-            t_p = timed(lambda: plan_p.solve([um], uT=[uT_plain], want_log=False), reps=1)
+            t_p = timed(lambda: plan_p.solve([um], uT=[uT_plain], want_log=False), reps=3, warm=1)
             del plan_p
             torch.cuda.empty_cache()
             extra["mixed_vs_plain_fp64"] = {
