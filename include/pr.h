@@ -153,7 +153,7 @@ int pr_parareal_update(int64_t npts, int32_t batch, int32_t sweep_dtype, const v
 
 /*
  * pr_defect_norm -- for each of `batch` field pairs (x_b, r_b) of npts values,
- * out4[b] = { max|x-r|, max|r|, sum (x-r)^2, sum r^2 } in FP64 (Section 2.2.4,
+ * out4[b] = { max|x-r|, max|r|, sum (x-r)^2, sum r^2 } in FP64 (Section 2.2.3,
  * eq. defect is out4[0]/out4[1]).  Deterministic: fixed partition and fixed
  * reduction order, independent of timing.  xd/rd: PR_FP32 or PR_FP64.
  *   out4  DEVICE array [batch][4] doubles

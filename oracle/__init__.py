@@ -41,7 +41,7 @@ class OrProb(ctypes.Structure):
                 ("nu0", ctypes.c_double), ("nu_amp", ctypes.c_double), ("nu_omega", ctypes.c_double),
                 ("T", ctypes.c_double),
                 ("P", ctypes.c_int32), ("nt_fine", ctypes.c_int32), ("nt_coarse", ctypes.c_int32),
-                ("nu_frozen", ctypes.c_int32)]
+                ("nu_frozen", ctypes.c_int32), ("coarsen", ctypes.c_int32), ("interp_order", ctypes.c_int32)]
 
 
 _lib = None
@@ -67,6 +67,10 @@ def lib():
         L.or_serial_coarse.argtypes = [pp, _dp, _dp, _dp]
         L.or_parareal.argtypes = [pp, ctypes.c_int, _dp, _dp, _dp, _dp]
         L.or_norms.argtypes = [ctypes.c_long, _dp, _dp, _dp]
+        L.or_restrict.argtypes = [pp, _dp, _dp]
+        L.or_restrict.restype = None
+        L.or_prolong.argtypes = [pp, ctypes.c_int, _dp, _dp]
+        L.or_prolong.restype = None
         L.or_threads.restype = ctypes.c_int
         for f in ("or_rk4_step_alloc", "or_euler_step_alloc", "or_fine_steps", "or_coarse_steps",
                   "or_serial_fine", "or_serial_coarse", "or_parareal"):
@@ -77,11 +81,14 @@ def lib():
 
 def _prob(p) -> OrProb:
     """Convert a workloads.Problem into the oracle's struct."""
-    nu_frozen = 1 if (int(getattr(p, "flags", 0)) & 1) else 0
+    flags = int(getattr(p, "flags", 0))
+    nu_frozen = 1 if flags & 1 else 0
+    coarsen = 1 if flags & 16 else 0
+    order = 3 if flags & 32 else 1
     return OrProb(int(p.n[0]), int(p.n[1]), int(p.n[2]), int(p.fine_order),
                   float(p.a[0]), float(p.a[1]), float(p.a[2]),
                   float(p.nu0), float(p.nu_amp), float(p.nu_omega), float(p.T),
-                  int(p.P), int(p.nt_fine), int(p.nt_coarse), nu_frozen)
+                  int(p.P), int(p.nt_fine), int(p.nt_coarse), nu_frozen, coarsen, order)
 
 
 def _ptr(a: np.ndarray):
@@ -94,6 +101,26 @@ def _field(p, u) -> np.ndarray:
     u = np.ascontiguousarray(u, dtype=np.float64)
     assert u.size == nx * ny * nz
     return u.reshape(nz, ny, nx)
+
+
+def restrict(p, u) -> np.ndarray:
+    """Injection onto the grid coarsened by 2 per direction ([nz/2, ny/2, nx/2])."""
+    s = _prob(p)
+    u = _field(p, u)
+    nx, ny, nz = (int(v) for v in p.n)
+    out = np.empty((nz // 2, ny // 2, nx // 2))
+    lib().or_restrict(ctypes.byref(s), _ptr(u), _ptr(out))
+    return out
+
+
+def prolong(p, uc, order: int = 1) -> np.ndarray:
+    """Interpolation (order 1 or 3) from the coarsened grid to the grid of p."""
+    s = _prob(p)
+    nx, ny, nz = (int(v) for v in p.n)
+    uc = np.ascontiguousarray(uc, dtype=np.float64).reshape(nz // 2, ny // 2, nx // 2)
+    out = np.empty((nz, ny, nx))
+    lib().or_prolong(ctypes.byref(s), int(order), _ptr(uc), _ptr(out))
+    return out
 
 
 def threads() -> int:

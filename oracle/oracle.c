@@ -14,7 +14,9 @@
  *   - fine propagator F: classical RK4 with centered differences; order 2
  *     (7-point) or order 4 (13-point, Section 3.1)     (Section 2.3, the fine-propagation item)
  *   - Parareal iteration                               (Section 2.2, eq. parareal; Algorithm 1)
- *   - norms of the defect                              (Section 2.2.4, eq. defect)
+ *   - optionally G on a spatially coarsened mesh with restriction and
+ *     interpolation                                    (Section 2.2.2, speedup-bound discussion)
+ *   - norms of the defect                              (Section 2.2.3, eq. defect)
  *
  * Readings taken where the paper is silent (listed in the design notes):
  *   - grid points x_i = i/n, periodic, h_d = 1/n_d, storage u[(z*ny + y)*nx + x];
@@ -26,7 +28,9 @@
  *   - the Euler loop of Algorithm 2 performs Nc steps (its loop bound counts
  *     Nc + 1);
  *   - the correction is evaluated as F + (G_new - G_old);
- *   - upwind for a_d == 0 takes the "else" branch (the term vanishes).
+ *   - upwind for a_d == 0 takes the "else" branch (the term vanishes);
+ *   - coarsened G: injection restriction, linear or cubic Lagrange
+ *     interpolation, the Euler steps of Algorithm 2 on the grid with h = 2/n.
  *
  * Floating point: IEEE binary64, round to nearest, built with
  * -O2 -ffp-contract=off and no fast-math.  Loops over z may run under OpenMP;
@@ -51,6 +55,8 @@ typedef struct {
     int32_t nt_fine;      /* fine steps on [0, T] */
     int32_t nt_coarse;    /* coarse steps on [0, T] */
     int32_t nu_frozen;    /* 1: nu(t_j) for all four RK4 stages */
+    int32_t coarsen;      /* 1: G runs on the grid coarsened by 2 in every direction */
+    int32_t interp_order; /* coarse -> fine interpolation: 1 (linear) or 3 (cubic) */
 } or_prob;
 
 /* Threads the z loops run on (1 without OpenMP). */
@@ -205,11 +211,100 @@ void or_fine_prop(const or_prob *p, int s, const double *u, double *out, double 
     for (int i = 0; i < nf; ++i) or_rk4_step(p, (long)s * nf + i, out, out, work);
 }
 
-/* G over time slice s: Nc = nt_coarse / P Euler steps starting at global step s*Nc. */
+/* Restriction to the grid coarsened by 2 in every direction, by injection:
+ * coarse point (x, y, z) takes the fine value at (2x, 2y, 2z).  Coarsening
+ * the spatial mesh of G is the option the paper names for a cheaper coarse
+ * propagator (Section 2.2.2, the discussion of the speedup bound); the paper
+ * fixes no transfer operators, injection is the simplest one. */
+void or_restrict(const or_prob *p, const double *u, double *uc)
+{
+    const int nx = p->nx, ny = p->ny, nz = p->nz;
+    const int cx = nx / 2, cy = ny / 2, cz = nz / 2;
+    for (int z = 0; z < cz; ++z)
+        for (int y = 0; y < cy; ++y)
+            for (int x = 0; x < cx; ++x)
+                uc[((long)z * cy + y) * cx + x] = u[((long)(2 * z) * ny + 2 * y) * nx + 2 * x];
+}
+
+/* One-dimensional interpolation taps from the coarse grid (size nc) to fine
+ * index i: an even index copies coarse point i/2; an odd index averages its
+ * two coarse neighbours (order 1) or takes the 4-point Lagrange midpoint
+ * rule -1/16, 9/16, 9/16, -1/16 (order 3).  Returns the number of taps. */
+static int interp_taps(int i, int nc, int order, int *idx, double *w)
+{
+    if (i % 2 == 0) {
+        idx[0] = i / 2;
+        w[0] = 1.0;
+        return 1;
+    }
+    const int m = (i - 1) / 2;   /* coarse neighbour on the left */
+    if (order == 1) {
+        idx[0] = wrap(m, nc);     w[0] = 0.5;
+        idx[1] = wrap(m + 1, nc); w[1] = 0.5;
+        return 2;
+    }
+    idx[0] = wrap(m - 1, nc); w[0] = -1.0 / 16.0;
+    idx[1] = wrap(m, nc);     w[1] = 9.0 / 16.0;
+    idx[2] = wrap(m + 1, nc); w[2] = 9.0 / 16.0;
+    idx[3] = wrap(m + 2, nc); w[3] = -1.0 / 16.0;
+    return 4;
+}
+
+/* Interpolation from the coarsened grid back to the fine grid: the tensor
+ * product of the 1-D taps, summed z-tap outermost, then y, then x, each term
+ * (wz*wy*wx) * value added in that order. */
+void or_prolong(const or_prob *p, int order, const double *uc, double *u)
+{
+    const int nx = p->nx, ny = p->ny, nz = p->nz;
+    const int cx = nx / 2, cy = ny / 2, cz = nz / 2;
+#pragma omp parallel for schedule(static)
+    for (int z = 0; z < nz; ++z) {
+        int iz[4], iy[4], ix[4];
+        double wz[4], wy[4], wx[4];
+        const int tz = interp_taps(z, cz, order, iz, wz);
+        for (int y = 0; y < ny; ++y) {
+            const int ty = interp_taps(y, cy, order, iy, wy);
+            for (int x = 0; x < nx; ++x) {
+                const int tx = interp_taps(x, cx, order, ix, wx);
+                double acc = 0.0;
+                for (int c = 0; c < tz; ++c)
+                    for (int b = 0; b < ty; ++b)
+                        for (int a = 0; a < tx; ++a)
+                            acc += (wz[c] * wy[b] * wx[a]) * uc[((long)iz[c] * cy + iy[b]) * cx + ix[a]];
+                u[((long)z * ny + y) * nx + x] = acc;
+            }
+        }
+    }
+}
+
+/* The problem on the coarsened grid: same physics and time grid, half the
+ * points per direction. */
+static or_prob coarsened(const or_prob *p)
+{
+    or_prob q = *p;
+    q.nx = p->nx / 2;
+    q.ny = p->ny / 2;
+    q.nz = p->nz / 2;
+    q.coarsen = 0;
+    return q;
+}
+
+/* G over time slice s: Nc = nt_coarse / P Euler steps starting at global step
+ * s*Nc.  With coarsening: restrict, the Nc Euler steps on the coarse grid,
+ * interpolate back.  work must hold npts doubles; u and out may alias. */
 void or_coarse_prop(const or_prob *p, int s, const double *u, double *out, double *work)
 {
     const long n = npts_of(p);
     const int nc = p->nt_coarse / p->P;
+    if (p->coarsen) {
+        const or_prob q = coarsened(p);
+        const long m = npts_of(&q);
+        double *uc = work, *wk = work + m;
+        or_restrict(p, u, uc);
+        for (int i = 0; i < nc; ++i) or_euler_step(&q, (long)s * nc + i, uc, uc, wk);
+        or_prolong(p, p->interp_order, uc, out);
+        return;
+    }
     memcpy(out, u, (size_t)n * sizeof(double));
     for (int i = 0; i < nc; ++i) or_euler_step(p, (long)s * nc + i, out, out, work);
 }
@@ -274,7 +369,7 @@ int or_serial_coarse(const or_prob *p, const double *u0, double *out, double *tr
  * U receives U^K_0..U^K_P ((P+1)*npts).  If hist is not NULL it receives every
  * iterate U^k_s, k = 0..K, as (K+1)*(P+1)*npts doubles.  If log is not NULL,
  * row k (8 doubles) holds the change between consecutive iterates (the
- * production monitor of Section 2.2.4): entries 0..3 are
+ * production monitor of Section 2.2.3): entries 0..3 are
  * {max|U^{k+1}_P - U^k_P|, max|U^{k+1}_P|, sum (U^{k+1}_P - U^k_P)^2,
  * sum (U^{k+1}_P)^2}; entries 4..7 the same quantities over all slices
  * s = 1..P (maxima of maxima, sums of sums).

@@ -15,7 +15,9 @@ therefore reduces, mode by mode, to scalar complex recurrences:
   * Parareal (eq. parareal) per mode:
         Z^{k+1}_{s+1} = g_s Z^{k+1}_s + f_s Z^k_s - g_s Z^k_s
 
-The grid field is the synthesis sum_q c_q Z_q e_q(x).  This path shares no
+The grid field is the synthesis sum_q c_q Z_q e_q(x); with G on a coarsened
+grid the recurrences couple the 8 aliases of a coarse mode (see below).  This
+path shares no
 code with oracle.c; agreement of the two pins both.  It also provides the
 continuous solution of the PDE (Section 3: u = a(t) u0(x - c t) with
 a(t) = exp(-4 pi^2 |kappa|^2 int_0^t nu)) for the discretisation-error checks.
@@ -213,6 +215,115 @@ class ModalSolution:
     def serial_coarse(self, s=None):
         s = self.p.P if s is None else s
         return synth(self.p.n, self.q, self.c * self.coarse[s])
+
+
+# ---------------------------------------------------------------------------
+# G on the grid coarsened by 2 per direction (restriction by injection,
+# Euler/upwind steps with h = 2/n, interpolation of order 1 or 3).
+#
+# Injection maps every fine exponential q to the coarse exponential q mod n/2,
+# so the 8 aliases q + (n/2) s, s in {0,1}^3, land on the same coarse mode.
+# Interpolating a coarse exponential b puts, per direction, the weight
+# (1 + c(theta))/2 on the fine exponentials b and b + n/2, with theta = 2 pi m/n
+# of that member and c = cos(theta) (linear midpoint average) or
+# (9 cos(theta) - cos(3 theta))/8 (4-point cubic midpoint rule).  Each alias
+# group is therefore invariant: F acts diagonally, the coarsened G as the
+# rank-one map x -> g alpha (sum of x), and Parareal runs on 8-vectors.
+# ---------------------------------------------------------------------------
+
+def interp_odd_factor(theta, order):
+    """Value of an interpolated exponential at an odd fine index, relative to
+    the exponential itself (one direction)."""
+    theta = np.asarray(theta, dtype=np.float64)
+    if order == 1:
+        return np.cos(theta)
+    if order == 3:
+        return (9.0 * np.cos(theta) - np.cos(3.0 * theta)) / 8.0
+    raise ValueError(order)
+
+
+def alias_groups(q, coef, n):
+    """Group fine exponentials by their coarse image.  Returns (members
+    [G, 8, 3] wavenumbers in [0, n), bases [G, 3], coefficients [G, 8])."""
+    nn = np.asarray([int(v) for v in n], dtype=np.int64)
+    half = nn // 2
+    qm = np.mod(np.asarray(q, dtype=np.int64), nn[None, :])
+    base = np.mod(qm, half[None, :])
+    sel = qm // half[None, :]
+    slot = sel[:, 0] + 2 * sel[:, 1] + 4 * sel[:, 2]
+    keys = {}
+    for b in map(tuple, base):
+        keys.setdefault(b, len(keys))
+    G = len(keys)
+    bases = np.zeros((G, 3), dtype=np.int64)
+    for b, gi in keys.items():
+        bases[gi] = b
+    svec = np.array([[m & 1, (m >> 1) & 1, (m >> 2) & 1] for m in range(8)], dtype=np.int64)
+    members = bases[:, None, :] + svec[None, :, :] * half[None, None, :]
+    C = np.zeros((G, 8), dtype=np.complex128)
+    for qi in range(qm.shape[0]):
+        C[keys[tuple(base[qi])], slot[qi]] += coef[qi]
+    return members, bases, C
+
+
+def coarsened_slice_factors(p, members, bases, order):
+    """(f [P, G, 8], g [P, G], alpha [G, 8]) for the coarsened G."""
+    P = p.P
+    Gn = members.shape[0]
+    RF = rk4_factors(p, members.reshape(-1, 3), 0, p.nt_fine)
+    f = np.stack([_prod_rows(RF[s * p.nf:(s + 1) * p.nf]) for s in range(P)]).reshape(P, Gn, 8)
+    half = [int(v) // 2 for v in p.n]
+    sD, sA = coarse_symbols(bases, half, p.a)
+    Dt = p.T / p.nt_coarse
+    g = np.ones((P, Gn), dtype=np.complex128)
+    for s in range(P):
+        for i in range(p.nc):
+            j = s * p.nc + i
+            g[s] = g[s] * (1.0 + Dt * (nu_of(p, j * Dt) * sD + sA))
+    nn = np.asarray([int(v) for v in p.n], dtype=np.float64)
+    theta = 2.0 * np.pi * members / nn[None, None, :]
+    alpha = np.prod(0.5 * (1.0 + interp_odd_factor(theta, order)), axis=2)
+    return f, g, alpha
+
+
+class CoarsenedModalSolution:
+    """All Parareal iterates with the spatially coarsened G, in modal form."""
+
+    def __init__(self, p, modes, order=1, K=None):
+        self.p = p
+        self.K = p.K if K is None else int(K)
+        q, c = expand_modes(modes)
+        self.members, self.bases, C = alias_groups(q, c, p.n)
+        f, g, alpha = coarsened_slice_factors(p, self.members, self.bases, order)
+        P, K = p.P, self.K
+
+        def G(s, x):
+            return g[s][:, None] * alpha * x.sum(axis=1)[:, None]
+
+        Z = np.zeros((K + 1, P + 1) + C.shape, dtype=np.complex128)
+        Z[0, 0] = C
+        for s in range(P):
+            Z[0, s + 1] = G(s, Z[0, s])
+        for k in range(K):
+            Z[k + 1, 0] = C
+            for s in range(P):
+                Z[k + 1, s + 1] = G(s, Z[k + 1, s]) + f[s] * Z[k, s] - G(s, Z[k, s])
+        self.Z = Z
+        self.fine = np.zeros((P + 1,) + C.shape, dtype=np.complex128)
+        self.fine[0] = C
+        for s in range(P):
+            self.fine[s + 1] = f[s] * self.fine[s]
+        self.q = self.members.reshape(-1, 3)
+
+    def iterate(self, k, s):
+        return synth(self.p.n, self.q, self.Z[k, s].reshape(-1))
+
+    def iterate_points(self, k, s, idx):
+        return synth_points(self.p.n, self.q, self.Z[k, s].reshape(-1), idx)
+
+    def serial_fine_points(self, idx, s=None):
+        s = self.p.P if s is None else s
+        return synth_points(self.p.n, self.q, self.fine[s].reshape(-1), idx)
 
 
 def analytic(p, modes, t):

@@ -1,6 +1,6 @@
 // Pointwise kernels: the Parareal correction (FP64), dtype casts and the
 // deterministic two-pass defect norms (Section 2.2, eq. parareal; Section
-// 2.2.4, eq. defect and the consecutive-iterate monitor).
+// 2.2.3, eq. defect and the consecutive-iterate monitor).
 //
 // Reductions use a fixed grid (kNormBlocks blocks per item, grid-stride
 // loop), a fixed butterfly inside each wavefront, a fixed order across the

@@ -44,6 +44,14 @@ MUTATIONS = [
      "tests/test_oracle_parareal.py::test_k_equals_p_is_serial_fine_bitwise"),
     ("slice start index", "or_rk4_step(p, (long)s * nf + i, out, out, work);", "or_rk4_step(p, (long)i, out, out, work);",
      "tests/test_oracle_time.py::test_slices_use_global_step_index"),
+    ("restriction offset", "u[((long)(2 * z) * ny + 2 * y) * nx + 2 * x]", "u[((long)(2 * z) * ny + 2 * y) * nx + 2 * x + 1]",
+     "tests/test_oracle_coarsened.py::test_restriction_samples_the_coarse_grid"),
+    ("cubic interpolation weight", "w[1] = 9.0 / 16.0;", "w[1] = 8.0 / 16.0;",
+     "tests/test_oracle_coarsened.py::test_interpolation_of_a_mode_closed_form"),
+    ("linear interpolation neighbour", "idx[1] = wrap(m + 1, nc); w[1] = 0.5;", "idx[1] = wrap(m, nc); w[1] = 0.5;",
+     "tests/test_oracle_coarsened.py::test_interpolation_of_a_mode_closed_form"),
+    ("coarsened G step index", "or_euler_step(&q, (long)s * nc + i, uc, uc, wk);", "or_euler_step(&q, (long)i, uc, uc, wk);",
+     "tests/test_oracle_coarsened.py::test_coarsened_parareal_matches_alias_group_model"),
 ]
 
 

@@ -30,6 +30,8 @@ NU_FROZEN = 1          # evaluate nu at the start of each RK4 step for all stage
 ALLOW_UNSTABLE = 2     # skip the coarse stability guard
 EARLY_STOP = 4
 SKIP_CONVERGED = 8     # reuse F/G results of slices that have already converged
+COARSEN_G = 16         # G on the grid coarsened by 2 per direction (injection, interpolation back)
+CUBIC_INTERP = 32      # with COARSEN_G: cubic instead of linear interpolation
 
 
 @dataclasses.dataclass
