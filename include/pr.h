@@ -70,6 +70,10 @@ extern "C" {
 #define PR_ALLOW_UNSTABLE 2u  /* skip the stability guard */
 #define PR_EARLY_STOP     4u  /* stop when max|U^{k+1}_P - U^k_P| <= tol * max|U^{k+1}_P| */
 #define PR_SKIP_CONVERGED 8u  /* do not recompute slices n < k in iteration k (bitwise identical result) */
+#define PR_COARSEN_G      16u /* plans: G runs on the grid coarsened by 2 per direction (every n_d even,
+                                 n_d/2 >= 3): injection, the Euler steps with h = 2/n, interpolation back
+                                 (Section 2.2.2 names a coarser mesh for G; the transfers are a reading) */
+#define PR_CUBIC_INTERP   32u /* with PR_COARSEN_G: cubic (4-point) instead of linear interpolation */
 
 /* One problem instance: the paper's problem statement (Section 2.1, Section 3). */
 typedef struct pr_problem {
@@ -84,7 +88,8 @@ typedef struct pr_problem {
     int32_t  nt_coarse;     /* coarse steps on [0,T]; multiple of P */
     int32_t  K;             /* Parareal iterations, 0 <= K <= P (K = 0 returns the coarse guess) */
     int32_t  fine_order;    /* 2 or 4 */
-    uint32_t flags;         /* PR_NU_FROZEN | PR_ALLOW_UNSTABLE | PR_EARLY_STOP | PR_SKIP_CONVERGED */
+    uint32_t flags;         /* PR_NU_FROZEN | PR_ALLOW_UNSTABLE | PR_EARLY_STOP | PR_SKIP_CONVERGED |
+                               PR_COARSEN_G | PR_CUBIC_INTERP */
     double   tol;           /* early-stop threshold (PR_EARLY_STOP) */
 } pr_problem;
 
@@ -139,6 +144,26 @@ int pr_coarse_sweep(const pr_problem *prob, int32_t dtype, int32_t batch, const 
 
 /* Workspace bytes needed by pr_fine_sweep / pr_coarse_sweep for these sizes. */
 size_t pr_sweep_workspace_bytes(const pr_problem *prob, int32_t dtype, int32_t batch);
+
+/*
+ * Grid transfers of the coarsened G (PR_COARSEN_G), on `batch` contiguous
+ * fields; prob gives the FINE grid (every n_d even, n_d/2 >= 3), dtype is
+ * PR_FP32 or PR_FP64 for input and output.
+ *   pr_restrict  u_coarse[(z*ny/2 + y)*nx/2 + x] = u_fine at (2x, 2y, 2z)
+ *                (injection); u_coarse holds batch * npts/8 values
+ *   pr_prolong   u_fine from u_coarse: per direction an even index copies
+ *                coarse point i/2, an odd index takes 1/2, 1/2 of its two
+ *                coarse neighbours (order 1) or -1/16, 9/16, 9/16, -1/16 of
+ *                four (order 3), periodic; the 3-D value is the tensor
+ *                product, summed z taps outermost, then y, then x
+ *   ws           workspace of pr_transfer_workspace_bytes(batch) bytes
+ * The coarse sweep in between is pr_coarse_sweep on the problem with n/2.
+ */
+size_t pr_transfer_workspace_bytes(int32_t batch);
+int pr_restrict(const pr_problem *prob, int32_t dtype, int32_t batch, const void *u_fine, void *u_coarse,
+                void *ws, size_t ws_bytes, void *stream);
+int pr_prolong(const pr_problem *prob, int32_t dtype, int32_t order, int32_t batch, const void *u_coarse,
+               void *u_fine, void *ws, size_t ws_bytes, void *stream);
 
 /*
  * pr_parareal_update -- the correction of eq. parareal / Algorithm 1 evaluated

@@ -12,12 +12,12 @@ from __future__ import annotations
 import ctypes
 
 from . import _lib as L
-from ._lib import (PR_ALLOW_UNSTABLE, PR_EARLY_STOP, PR_FP32, PR_FP64, PR_MODE_FP64,  # noqa: F401
-                   PR_MODE_GRAPH, PR_MODE_MIXED, PR_MODE_PER_SLICE, PR_MODE_TIMED, PR_NU_FROZEN,
-                   PR_SKIP_CONVERGED, PrError, check, lib, to_struct)
+from ._lib import (PR_ALLOW_UNSTABLE, PR_COARSEN_G, PR_CUBIC_INTERP, PR_EARLY_STOP, PR_FP32,  # noqa: F401
+                   PR_FP64, PR_MODE_FP64, PR_MODE_GRAPH, PR_MODE_MIXED, PR_MODE_PER_SLICE, PR_MODE_TIMED,
+                   PR_NU_FROZEN, PR_SKIP_CONVERGED, PrError, check, lib, to_struct)
 
-__all__ = ["fine_sweep", "coarse_sweep", "parareal_update", "defect_norm", "Plan", "check_stability",
-           "set_kernel_variant", "variants", "autotune", "PrError", "lib"]
+__all__ = ["fine_sweep", "coarse_sweep", "parareal_update", "defect_norm", "restrict", "prolong", "Plan",
+           "check_stability", "set_kernel_variant", "variants", "autotune", "PrError", "lib"]
 
 
 def _torch():
@@ -81,6 +81,38 @@ def fine_sweep(prob, u_in, step0, nsteps, u_out=None, stream=None):
 def coarse_sweep(prob, u_in, step0, nsteps, u_out=None, stream=None):
     """nsteps forward Euler / upwind steps of G (Algorithm 2)."""
     return _sweep(lib().pr_coarse_sweep, prob, u_in, step0, nsteps, u_out, stream)
+
+
+def _transfer(prob, u_in, order, prolong, stream):
+    torch = _torch()
+    s = to_struct(prob)
+    nx, ny, nz = (int(v) for v in prob.n)
+    fine, coarse = nx * ny * nz, (nx // 2) * (ny // 2) * (nz // 2)
+    n_in = coarse if prolong else fine
+    if u_in.numel() % n_in:
+        raise ValueError("input size is not a multiple of the %s grid size" % ("coarse" if prolong else "fine"))
+    batch = u_in.numel() // n_in
+    shape = (batch, nz, ny, nx) if prolong else (batch, nz // 2, ny // 2, nx // 2)
+    out = torch.empty(shape, dtype=u_in.dtype, device=u_in.device)
+    ws = _workspace(lib().pr_transfer_workspace_bytes(batch), u_in.device)
+    dt = _code(u_in)
+    if prolong:
+        check(lib().pr_prolong(ctypes.byref(s), dt, int(order), batch, _dev(u_in), _dev(out),
+                               ctypes.c_void_p(ws.data_ptr()), ws.numel(), _stream_ptr(stream)))
+    else:
+        check(lib().pr_restrict(ctypes.byref(s), dt, batch, _dev(u_in), _dev(out), ctypes.c_void_p(ws.data_ptr()),
+                                ws.numel(), _stream_ptr(stream)))
+    return out
+
+
+def restrict(prob, u_fine, stream=None):
+    """Injection of fine fields (grid of prob) onto the grid coarsened by 2: [batch, nz/2, ny/2, nx/2]."""
+    return _transfer(prob, u_fine, 1, False, stream)
+
+
+def prolong(prob, u_coarse, order=1, stream=None):
+    """Interpolation (order 1 or 3) of coarse fields to the grid of prob: [batch, nz, ny, nx]."""
+    return _transfer(prob, u_coarse, order, True, stream)
 
 
 def parareal_update(f_new, g_new, g_old, u_out=None, u_out_lo=None, stream=None):

@@ -100,10 +100,31 @@ int validate_problem(const pr_problem *p, bool need_parareal)
         if (p->K < 0 || p->K > p->P) return fail(PR_EINVAL, "K = %d outside [0, P = %d]", p->K, p->P);
         if ((p->flags & PR_EARLY_STOP) && !(p->tol >= 0.0)) return fail(PR_EINVAL, "tol must be >= 0");
     }
-    if (p->flags & ~(PR_NU_FROZEN | PR_ALLOW_UNSTABLE | PR_EARLY_STOP | PR_SKIP_CONVERGED))
+    if (p->flags & ~(PR_NU_FROZEN | PR_ALLOW_UNSTABLE | PR_EARLY_STOP | PR_SKIP_CONVERGED | PR_COARSEN_G |
+                     PR_CUBIC_INTERP))
         return fail(PR_EINVAL, "unknown flag bits 0x%x", p->flags);
+    if ((p->flags & PR_CUBIC_INTERP) && !(p->flags & PR_COARSEN_G))
+        return fail(PR_EINVAL, "PR_CUBIC_INTERP needs PR_COARSEN_G");
+    if (p->flags & PR_COARSEN_G)
+        for (int d = 0; d < 3; ++d)
+            if (p->n[d] % 2 != 0 || p->n[d] / 2 < 3)
+                return fail(PR_EINVAL, "PR_COARSEN_G needs even n[d] >= 6 (n[%d] = %d)", d, p->n[d]);
     return PR_OK;
 }
+
+// The grid G runs on: the problem's own, or with PR_COARSEN_G the grid
+// coarsened by 2 per direction (same physics and time grid).
+pr_problem coarse_grid(const pr_problem &p)
+{
+    pr_problem q = p;
+    if (p.flags & PR_COARSEN_G) {
+        for (int d = 0; d < 3; ++d) q.n[d] = p.n[d] / 2;
+        q.flags &= ~(PR_COARSEN_G | PR_CUBIC_INTERP);
+    }
+    return q;
+}
+
+int interp_order(const pr_problem &p) { return (p.flags & PR_CUBIC_INTERP) ? 3 : 1; }
 
 // ---- stability ------------------------------------------------------------
 
@@ -112,9 +133,10 @@ void margins(const pr_problem &p, double *fm, double *cm)
     const double numax = p.nu0 * (1.0 + std::fabs(p.nu_amp));
     const double numin = p.nu0 * (1.0 - std::fabs(p.nu_amp));
     double sa = 0.0, sd = 0.0;
+    const pr_problem g = coarse_grid(p);   // G's grid
     for (int d = 0; d < 3; ++d) {
-        sa += std::fabs(p.a[d]) * p.n[d];
-        sd += (double)p.n[d] * p.n[d];
+        sa += std::fabs(g.a[d]) * g.n[d];
+        sd += (double)g.n[d] * g.n[d];
     }
     const double Dt = p.T / p.nt_coarse;
     *cm = Dt * (sa + 2.0 * numax * sd);
@@ -163,7 +185,7 @@ void margins_cached(const pr_problem &p, double *fm, double *cm)
 {
     const std::vector<double> key = {(double)p.n[0], (double)p.n[1], (double)p.n[2], p.a[0], p.a[1], p.a[2],
                                      p.nu0, p.nu_amp, p.T, (double)p.nt_fine, (double)p.nt_coarse,
-                                     (double)p.fine_order};
+                                     (double)p.fine_order, (double)(p.flags & PR_COARSEN_G)};
     {
         std::lock_guard<std::mutex> lk(g_margin_mu);
         auto it = g_margin_cache.find(key);
@@ -353,11 +375,15 @@ size_t sweep_ws(const pr_problem &p, int dtype, int batch, bool fine_ref)
     return align256((size_t)batch * sizeof(ItemDesc)) + align256(states) + (fine_ref ? 3 * align256(states) : 0);
 }
 
-int sweep_common(const pr_problem *prob, int dtype, int batch, const void *u_in, void *u_out, const int64_t *step0,
-                 int nsteps, void *ws, size_t ws_bytes, void *stream, bool fine)
+int sweep_common(const pr_problem *prob_in, int dtype, int batch, const void *u_in, void *u_out,
+                 const int64_t *step0, int nsteps, void *ws, size_t ws_bytes, void *stream, bool fine)
 {
-    int rc = validate_problem(prob, false);
+    int rc = validate_problem(prob_in, false);
     if (rc) return rc;
+    // a sweep runs on the grid it is given: the plan-level coarsening flags do not apply
+    pr_problem local = *prob_in;
+    local.flags &= ~(PR_COARSEN_G | PR_CUBIC_INTERP);
+    const pr_problem *prob = &local;
     if (dtype != PR_FP32 && dtype != PR_FP64) return fail(PR_EINVAL, "dtype must be PR_FP32 or PR_FP64");
     if (batch < 1) return fail(PR_EINVAL, "batch must be >= 1");
     if (nsteps < 0) return fail(PR_EINVAL, "nsteps must be >= 0");
@@ -440,6 +466,7 @@ struct pr_plan {
         double *U;                 // (P+1) FP64 states
         char *Ulo;                 // (P+1) sweep states (== U in FP64 mode)
         char *Fv, *Ftmp, *Gold[2], *Gtmp, *Fscr;
+        char *Cin, *Cout, *Ctmp;   // coarsened G: restricted input, coarse result, ping-pong (npts/8 each)
         double *part;              // P x kNormBlocks x 4 correction partials
         double *refpart;           // kNormBlocks x 4
     };
@@ -453,6 +480,10 @@ struct pr_plan {
     std::vector<int> slice_index;       // (i, n) -> index into slice_tab
     std::vector<int> slice_blocks;      // blocks of each slice_tab item
     ItemDesc *coarse_tab = nullptr;     // [parity][n] -> up to ninst items
+    bool coarsen = false;               // PR_COARSEN_G: G = prolong(coarse sweep(restrict(U)))
+    int iorder = 1;                     // interpolation order of the coarsened G
+    ItemDesc *rst_tab = nullptr;        // [n][ninst] restriction U_n -> Cin
+    ItemDesc *pro_tab = nullptr;        // [parity][n][ninst] interpolation Cout -> Gold[parity]_n
     std::vector<int> coarse_cnt;        // per n: items (instances with P_i > n)
     std::vector<int> coarse_blocks;     // per (parity, n)
     std::vector<int> coarse_nch;        // per n: chunks of the longest item
@@ -519,6 +550,10 @@ size_t plan_layout(const pr_problem *probs, int ninst, int mode, char *base, pr_
         in.Gold[1] = take(p.P * n * es);
         in.Gtmp = take(n * es);
         in.Fscr = fine_ref ? take(3 * p.P * n * es) : nullptr;
+        const bool crs = (p.flags & PR_COARSEN_G) != 0;
+        in.Cin = crs ? take(n / 8 * es) : nullptr;
+        in.Cout = crs ? take(n / 8 * es) : nullptr;
+        in.Ctmp = crs ? take(n / 8 * es) : nullptr;
         in.part = (double *)take((size_t)p.P * pr::kNormBlocks * 4 * 8);
         in.refpart = (double *)take((size_t)pr::kNormBlocks * 4 * 8);
         if (plan) plan->inst.push_back(in);
@@ -527,6 +562,8 @@ size_t plan_layout(const pr_problem *probs, int ninst, int mode, char *base, pr_
     char *fine_tab = take((size_t)Kt * sumP * sizeof(ItemDesc));
     char *slice_tab = take((size_t)sumP * sizeof(ItemDesc));
     char *coarse_tab = take((size_t)2 * Pmax * ninst * sizeof(ItemDesc));
+    char *rst_tab = take((size_t)Pmax * ninst * sizeof(ItemDesc));
+    char *pro_tab = take((size_t)2 * Pmax * ninst * sizeof(ItemDesc));
     char *pt_assign = take((size_t)Pmax * ninst * sizeof(PointItem));
     char *pt_corr = take((size_t)2 * Pmax * ninst * sizeof(PointItem));
     char *pt_skip = take((size_t)2 * Pmax * ninst * sizeof(PointItem));
@@ -540,6 +577,8 @@ size_t plan_layout(const pr_problem *probs, int ninst, int mode, char *base, pr_
         plan->fine_tab = (ItemDesc *)fine_tab;
         plan->slice_tab = (ItemDesc *)slice_tab;
         plan->coarse_tab = (ItemDesc *)coarse_tab;
+        plan->rst_tab = (ItemDesc *)rst_tab;
+        plan->pro_tab = (ItemDesc *)pro_tab;
         plan->pt_assign = (PointItem *)pt_assign;
         plan->pt_corr = (PointItem *)pt_corr;
         plan->pt_skip = (PointItem *)pt_skip;
@@ -662,9 +701,12 @@ int build_tables(pr_plan *pl)
     rc = upload(pl->slice_tab, sl);
     if (rc) return rc;
 
-    // coarse tables [parity][n]: instances with P_i > n
+    // coarse tables [parity][n]: instances with P_i > n.  With coarsening the
+    // sweep runs on the coarsened grid from Cin to Cout, bracketed by the
+    // restriction [n] and the interpolation [parity][n] tables.
     const int Pmax = pl->Pmax;
     std::vector<ItemDesc> ct((size_t)2 * Pmax * ninst);
+    std::vector<ItemDesc> rt((size_t)Pmax * ninst), pt((size_t)2 * Pmax * ninst);
     pl->coarse_cnt.assign(Pmax, 0);
     pl->coarse_blocks.assign(2 * Pmax, 0);
     pl->coarse_nch.assign(Pmax, 0);
@@ -677,13 +719,27 @@ int build_tables(pr_plan *pl)
                 if (n >= in.P) continue;
                 ItemDesc it;
                 std::memset(&it, 0, sizeof it);
-                fill_item(it, pl->probs[i], false);
-                it.src0 = slice_ptr(in.Ulo, n, in.npts, es);
-                it.dst = slice_ptr(in.Gold[par], n, in.npts, es);
-                it.tmp = in.Gtmp;
+                fill_item(it, coarse_grid(pl->probs[i]), false);
+                it.src0 = pl->coarsen ? in.Cin : slice_ptr(in.Ulo, n, in.npts, es);
+                it.dst = pl->coarsen ? in.Cout : slice_ptr(in.Gold[par], n, in.npts, es);
+                it.tmp = pl->coarsen ? in.Ctmp : in.Gtmp;
                 it.step0 = (int64_t)n * in.nc;
                 it.nsteps = in.nc;
                 items.push_back(it);
+                if (pl->coarsen) {
+                    const int m = (int)items.size() - 1;
+                    ItemDesc x;
+                    std::memset(&x, 0, sizeof x);
+                    x.nx = pl->probs[i].n[0];
+                    x.ny = pl->probs[i].n[1];
+                    x.nz = pl->probs[i].n[2];
+                    x.src0 = slice_ptr(in.Ulo, n, in.npts, es);
+                    x.dst = in.Cin;
+                    if (par == 0) rt[(size_t)n * ninst + m] = x;
+                    x.src0 = in.Cout;
+                    x.dst = slice_ptr(in.Gold[par], n, in.npts, es);
+                    pt[((size_t)par * Pmax + n) * ninst + m] = x;
+                }
             }
             std::stable_sort(items.begin(), items.end(),
                              [](const ItemDesc &a, const ItemDesc &b) { return a.nsteps > b.nsteps; });
@@ -695,6 +751,12 @@ int build_tables(pr_plan *pl)
         }
     rc = upload(pl->coarse_tab, ct);
     if (rc) return rc;
+    if (pl->coarsen) {
+        rc = upload(pl->rst_tab, rt);
+        if (rc) return rc;
+        rc = upload(pl->pro_tab, pt);
+        if (rc) return rc;
+    }
 
     // pointwise tables
     std::vector<PointItem> assign((size_t)Pmax * ninst), corr((size_t)2 * Pmax * ninst),
@@ -755,8 +817,11 @@ int enqueue_init(pr_plan *pl, hipStream_t s)
         const int cnt = pl->coarse_cnt[n];
         if (!cnt) continue;
         const ItemDesc *tab = pl->coarse_tab + (size_t)(0 * Pmax + n) * ninst;
+        if (pl->coarsen) HIPCHK(pr::launch_restrict(pl->dtype, pl->rst_tab + (size_t)n * ninst, cnt, s));
         for (int c = 0; c < pl->coarse_nch[n]; ++c)
             HIPCHK(pr::launch_coarse_chunk(pl->coarse_v, pl->dtype, tab, cnt, pl->coarse_blocks[n], c, s));
+        if (pl->coarsen)
+            HIPCHK(pr::launch_prolong(pl->dtype, pl->iorder, pl->pro_tab + (size_t)(0 * Pmax + n) * ninst, cnt, s));
         HIPCHK(pr::launch_pointwise(pr::kOpAssign, pl->dtype, pl->pt_assign + (size_t)n * ninst, cnt, false, s));
     }
     return PR_OK;
@@ -808,8 +873,12 @@ int enqueue_iteration(pr_plan *pl, int k, hipStream_t s, bool with_ref)
         }
         const int cpar = 1 - par;  // G_new goes to Gold[1 - k%2]
         const ItemDesc *tab = pl->coarse_tab + ((size_t)cpar * Pmax + n) * ninst;
+        if (pl->coarsen) HIPCHK(pr::launch_restrict(pl->dtype, pl->rst_tab + (size_t)n * ninst, cnt, s));
         for (int c = 0; c < pl->coarse_nch[n]; ++c)
             HIPCHK(pr::launch_coarse_chunk(pl->coarse_v, pl->dtype, tab, cnt, pl->coarse_blocks[cpar * Pmax + n], c, s));
+        if (pl->coarsen)
+            HIPCHK(pr::launch_prolong(pl->dtype, pl->iorder, pl->pro_tab + ((size_t)cpar * Pmax + n) * ninst, cnt,
+                                      s));
         HIPCHK(pr::launch_pointwise(pr::kOpCorrect, pl->dtype, pl->pt_corr + ((size_t)par * Pmax + n) * ninst, cnt,
                                     true, s));
     }
@@ -911,6 +980,62 @@ int pr_coarse_sweep(const pr_problem *prob, int32_t dtype, int32_t batch, const 
     return sweep_common(prob, dtype, batch, u_in, u_out, step0, nsteps, ws, ws_bytes, stream, false);
 }
 
+size_t pr_transfer_workspace_bytes(int32_t batch)
+{
+    if (batch < 1) return 0;
+    return align256((size_t)batch * sizeof(ItemDesc));
+}
+
+static int transfer_common(const pr_problem *prob, int dtype, int order, int batch, const void *in, void *out,
+                           void *ws, size_t ws_bytes, void *stream, bool prolong)
+{
+    if (!prob) return fail(PR_EINVAL, "problem is NULL");
+    pr_problem p = *prob;
+    p.flags = PR_COARSEN_G;   // only the grid matters here
+    int rc = validate_problem(&p, false);
+    if (rc) return rc;
+    if (dtype != PR_FP32 && dtype != PR_FP64) return fail(PR_EINVAL, "dtype must be PR_FP32 or PR_FP64");
+    if (prolong && order != 1 && order != 3) return fail(PR_EINVAL, "interpolation order must be 1 or 3");
+    if (batch < 1) return fail(PR_EINVAL, "batch must be >= 1");
+    if (!in || !out) return fail(PR_EINVAL, "NULL field pointer");
+    const size_t fb = (size_t)npts_of(p) * esize(dtype), cb = fb / 8;
+    const size_t inb = (prolong ? cb : fb) * batch, outb = (prolong ? fb : cb) * batch;
+    const char *a = (const char *)in, *o = (const char *)out;
+    if (a < o + outb && o < a + inb) return fail(PR_EINVAL, "input and output overlap");
+    const size_t need = pr_transfer_workspace_bytes(batch);
+    if (!ws || ws_bytes < need) return fail(PR_ENOMEM, "workspace of %zu bytes < %zu needed", ws_bytes, need);
+    rc = device_ready();
+    if (rc) return rc;
+    std::vector<ItemDesc> items(batch);
+    for (int b = 0; b < batch; ++b) {
+        ItemDesc &it = items[b];
+        std::memset(&it, 0, sizeof it);
+        it.nx = p.n[0];
+        it.ny = p.n[1];
+        it.nz = p.n[2];
+        it.src0 = a + b * (prolong ? cb : fb);
+        it.dst = (char *)out + b * (prolong ? fb : cb);
+    }
+    hipStream_t s = (hipStream_t)stream;
+    ItemDesc *table = (ItemDesc *)ws;
+    HIPCHK(pr::launch_write_items(items.data(), batch, table, s));
+    if (prolong) HIPCHK(pr::launch_prolong(dtype, order, table, batch, s));
+    else HIPCHK(pr::launch_restrict(dtype, table, batch, s));
+    return PR_OK;
+}
+
+int pr_restrict(const pr_problem *prob, int32_t dtype, int32_t batch, const void *u_fine, void *u_coarse, void *ws,
+                size_t ws_bytes, void *stream)
+{
+    return transfer_common(prob, dtype, 1, batch, u_fine, u_coarse, ws, ws_bytes, stream, false);
+}
+
+int pr_prolong(const pr_problem *prob, int32_t dtype, int32_t order, int32_t batch, const void *u_coarse,
+               void *u_fine, void *ws, size_t ws_bytes, void *stream)
+{
+    return transfer_common(prob, dtype, order, batch, u_coarse, u_fine, ws, ws_bytes, stream, true);
+}
+
 int pr_parareal_update(int64_t npts, int32_t batch, int32_t sweep_dtype, const void *f_new, const void *g_new,
                        const void *g_old, double *u_out, void *u_out_lo, void *stream)
 {
@@ -997,14 +1122,16 @@ int pr_plan_create(const pr_problem *probs, int32_t ninst, int32_t mode, void *w
     pl->timed = (mode & PR_MODE_TIMED) != 0;
     pl->graph = (mode & PR_MODE_GRAPH) != 0 && !pl->early && !pl->timed;
     pl->probs.assign(probs, probs + ninst);
+    pl->coarsen = (pl->flags & PR_COARSEN_G) != 0;
+    pl->iorder = interp_order(probs[0]);
 
     // one fused variant for all instances: the choice for instance 0 if it
     // applies to every instance, else the generic one-point-per-thread layout
-    int fv = pick_fine(probs[0], pl->dtype), cv = pick_coarse(probs[0], pl->dtype);
+    int fv = pick_fine(probs[0], pl->dtype), cv = pick_coarse(coarse_grid(probs[0]), pl->dtype);
     bool fok = fv >= 1, cok = cv >= 1;
     for (int i = 0; i < ninst; ++i) {
         fok = fok && fine_applicable(fv, pl->dtype, probs[i].fine_order, probs[i]);
-        cok = cok && coarse_applicable(cv, pl->dtype, probs[i]);
+        cok = cok && coarse_applicable(cv, pl->dtype, coarse_grid(probs[i]));
         if (probs[i].fine_order != probs[0].fine_order) {
             delete pl;
             return fail(PR_EUNSUPPORTED, "instances of one plan must share fine_order");
@@ -1012,12 +1139,17 @@ int pr_plan_create(const pr_problem *probs, int32_t ninst, int32_t mode, void *w
     }
     // fallback: the tiled default for a generic n_x, even if every instance
     // has an even n_x (two x points per thread), else odd (one per thread)
-    bool all_even = true;
-    for (int i = 0; i < ninst; ++i) all_even = all_even && probs[i].n[0] % 2 == 0;
+    bool all_even = true, all_even_c = true;
+    for (int i = 0; i < ninst; ++i) {
+        all_even = all_even && probs[i].n[0] % 2 == 0;
+        all_even_c = all_even_c && coarse_grid(probs[i]).n[0] % 2 == 0;
+    }
     pr_problem generic = probs[0];
     generic.n[0] = all_even ? 2 : 3;
+    pr_problem generic_c = coarse_grid(probs[0]);
+    generic_c.n[0] = all_even_c ? 2 : 3;
     if (!fok) fv = g_fine_forced ? -1 : pick_fine_default(generic, pl->dtype);
-    if (!cok) cv = g_coarse_forced ? -1 : pick_coarse_default(generic, pl->dtype);
+    if (!cok) cv = g_coarse_forced ? -1 : pick_coarse_default(generic_c, pl->dtype);
     if (fv < 1 || cv < 1) {
         delete pl;
         return fail(PR_EUNSUPPORTED, "forced kernel variant does not apply to every instance");

@@ -72,6 +72,12 @@ const VariantInfo *fine_variant(int v);      // v >= 2
 int coarse_variant_count();
 const VariantInfo *coarse_variant(int v);    // v >= 2
 
+// Grid transfers of the coarsened G over tables of ItemDesc (src0 -> dst,
+// nx/ny/nz of the fine grid): injection to the grid coarsened by 2, and
+// interpolation of order 1 or 3 back to the fine grid.
+hipError_t launch_restrict(int dtype, const ItemDesc *items, int nitems, hipStream_t s);
+hipError_t launch_prolong(int dtype, int order, const ItemDesc *items, int nitems, hipStream_t s);
+
 // Pointwise kernels over tables of PointItem (blockIdx.y = item).
 enum PointOp { kOpCorrect = 0, kOpAssign = 1, kOpCopy64 = 2 };
 //   kOpCorrect: u = a + (b - c) in FP64 (a, b, c of sweep dtype); ulo = (T)u;

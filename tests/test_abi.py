@@ -208,3 +208,45 @@ def test_whole_row_variant_rejects_other_nx():
     finally:
         L.lib().pr_set_kernel_variant(0, 0)
     assert rc == L.PR_EUNSUPPORTED
+
+
+def test_coarsened_g_validation_and_margin():
+    """PR_COARSEN_G needs even n >= 6 per direction and takes the coarse
+    stability margin on the coarsened grid (h = 2/n): the 128^3 workload's G
+    with 128 coarse steps is unstable on the fine grid and stable when
+    coarsened.  PR_CUBIC_INTERP alone is rejected."""
+    import paper_1409_8563_amd as pr
+    L = _lib()
+    p, _ = W.config("c2_128_fp64")
+    p.nt_coarse = 128
+    rc, fm, cm_fine = pr.check_stability(p)
+    assert rc == L.PR_EUNSTABLE and cm_fine > 1.0
+    p.flags = W.COARSEN_G
+    rc, fm, cm = pr.check_stability(p)
+    assert rc == 0 and cm < 1.0
+    # the coarsened margin is the same bound evaluated with n/2
+    nm = p.nu0 * (1 + abs(p.nu_amp))
+    ref = (p.T / p.nt_coarse) * sum(abs(p.a[d]) * 64 + 2 * nm * 64 * 64 for d in range(3))
+    assert abs(cm - ref) <= 1e-12 * ref
+    arr = (L.PrProblem * 1)(L.to_struct(p))
+    assert L.lib().pr_plan_workspace_bytes(arr, 1, 0) > 0
+    q = W.small_problem(n=(10, 7, 8), P=2, nf=8, nc=8, flags=W.COARSEN_G)
+    arr = (L.PrProblem * 1)(L.to_struct(q))
+    assert L.lib().pr_plan_workspace_bytes(arr, 1, 0) == 0 and "even" in L.last_error()
+    q = W.small_problem(n=(10, 8, 8), P=2, nf=8, nc=8, flags=W.CUBIC_INTERP)
+    arr = (L.PrProblem * 1)(L.to_struct(q))
+    assert L.lib().pr_plan_workspace_bytes(arr, 1, 0) == 0 and "PR_COARSEN_G" in L.last_error()
+
+
+def test_grid_transfer_validation_without_device():
+    L = _lib()
+    p = W.small_problem(n=(12, 10, 8), P=2)
+    s = L.to_struct(p)
+    big = 1 << 30
+    assert L.lib().pr_transfer_workspace_bytes(3) >= 3 * 8
+    assert L.lib().pr_prolong(ctypes.byref(s), 2, 2, 1, 16, 16 + big, 16, 1 << 20, None) == L.PR_EINVAL
+    assert L.lib().pr_restrict(ctypes.byref(s), 2, 1, 16, 16 + big, 16, 0, None) == L.PR_ENOMEM
+    assert L.lib().pr_restrict(ctypes.byref(s), 2, 1, 16, 16 + 8, 16, 1 << 20, None) == L.PR_EINVAL  # overlap
+    q = W.small_problem(n=(12, 9, 8), P=2)
+    s = L.to_struct(q)
+    assert L.lib().pr_restrict(ctypes.byref(s), 2, 1, 16, 16 + big, 16, 1 << 20, None) == L.PR_EINVAL

@@ -326,6 +326,69 @@ def test_parareal_mixed_against_oracle(pr, orc):
         assert rel_l2(states[0][n], U[n]) <= FP32_TOL, n
 
 
+@pytest.mark.parametrize("dtype", [1, 2])
+@pytest.mark.parametrize("order", [1, 3])
+def test_grid_transfers_against_oracle(pr, orc, dtype, order):
+    """Restriction (injection) and interpolation of the coarsened G, batch of
+    two fields, against the oracle: bitwise in FP64 (same terms in the same
+    order), within FP32 rounding otherwise."""
+    import torch
+    tdt = torch.float64 if dtype == 2 else torch.float32
+    p = W.small_problem(n=(36, 20, 14))
+    u = np.stack([W.random_field(p.n, 230 + b) for b in range(2)])
+    say("grid transfers", dtype, order)
+    uc = np.stack([orc.restrict(p, u[b]) for b in range(2)])
+    f = np.stack([orc.prolong(p, uc[b], order) for b in range(2)])
+    gr = host(pr.restrict(p, cuda(u, tdt)))
+    gf = host(pr.prolong(p, cuda(uc, tdt), order))
+    if dtype == 2:
+        assert np.array_equal(gr, uc) and np.array_equal(gf, f)
+    else:
+        assert np.array_equal(gr, uc.astype(np.float32).astype(np.float64))
+        assert rel_l2(gf, f) <= 1e-6
+
+
+@pytest.mark.parametrize("flags", [W.COARSEN_G, W.COARSEN_G | W.CUBIC_INTERP])
+def test_parareal_coarsened_g_against_oracle(pr, orc, flags):
+    """Parareal with G on the grid coarsened by 2 (linear or cubic transfer):
+    every slice state for K = 0, 2, P against the oracle, mixed precision
+    within the FP32 bar, and eager / per-slice / skip / graph replay bitwise
+    identical."""
+    import torch
+    p = W.small_problem(n=(32, 24, 20), a=(0.8, -0.5, 0.3), nu0=0.004, P=4, nf=8, nc=4, K=4, flags=flags)
+    modes = W.draw_modes(np.random.default_rng(240), 6, 3)
+    u0 = W.synth_u0(p.n, modes)
+    _, _, hist = orc.parareal(p, u0, K=p.P, history=True)
+    for K in (0, 2, p.P):
+        say("coarsened G", flags, "K", K)
+        p.K = K
+        _, _, states, _ = _solve(pr, [p], [u0], pr.PR_MODE_FP64)
+        for n in range(p.P + 1):
+            assert rel_l2(states[0][n], hist[K, n]) <= FP64_TOL, (K, n)
+    p.K = 2
+    say("coarsened G mixed")
+    _, _, states, _ = _solve(pr, [p], [u0], pr.PR_MODE_MIXED)
+    for n in range(p.P + 1):
+        assert rel_l2(states[0][n], hist[2, n]) <= FP32_TOL, n
+    say("coarsened G modes")
+    base, blog, _, _ = _solve(pr, [p], [u0], pr.PR_MODE_FP64)
+    ps, plog, _, _ = _solve(pr, [p], [u0], pr.PR_MODE_FP64 | pr.PR_MODE_PER_SLICE)
+    assert np.array_equal(ps[0], base[0]) and np.array_equal(plog, blog)
+    q = W.small_problem(n=(32, 24, 20), a=(0.8, -0.5, 0.3), nu0=0.004, P=4, nf=8, nc=4, K=2,
+                        flags=flags | W.SKIP_CONVERGED)
+    sk, _, _, _ = _solve(pr, [q], [u0], pr.PR_MODE_FP64)
+    assert np.array_equal(sk[0], base[0])
+    plan = pr.Plan([p], pr.PR_MODE_FP64 | pr.PR_MODE_GRAPH)
+    x = cuda(u0)
+    for rep in range(3):
+        uT, glog = plan.solve([x])
+        scratch = torch.randn(1000, device="cuda").sum()
+        torch.cuda.synchronize()
+        assert np.array_equal(host(uT[0]), base[0]), rep
+        assert np.array_equal(glog, blog), rep
+        del scratch
+
+
 def test_multi_instance_uneven(pr, orc):
     """Instances of different sizes, coefficients and step counts in one plan:
     each equals its own single-instance solve bitwise and the oracle to 1e-12."""
@@ -427,6 +490,26 @@ def test_full_size_c2_fp64(pr):
         ref = ms.iterate_points(p.K, n, idx)
         assert rel_l2(got, ref) <= FP64_TOL, n
     assert rel_l2(_at(uT[0], idx), ms.iterate_points(p.K, p.P, idx)) <= FP64_TOL
+
+
+@pytest.mark.parametrize("cubic", [False, True])
+def test_full_size_c2_coarsened_g(pr, cubic):
+    """The 128^3 FP64 workload with G on the 64^3 grid (128 coarse steps, the
+    smallest power of two the coarsened grid keeps stable), every slice state
+    at sampled points against the alias-group modal solution."""
+    from oracle import spectral as S
+    say("c2 coarsened", cubic)
+    p, modes = W.config("c2_128_fp64")
+    p.nt_coarse = 128
+    p.flags = W.COARSEN_G | (W.CUBIC_INTERP if cubic else 0)
+    u0 = W.synth_u0(p.n, modes)
+    ms = S.CoarsenedModalSolution(p, modes, order=3 if cubic else 1)
+    plan = pr.Plan([p], pr.PR_MODE_FP64)
+    plan.solve([cuda(u0)])
+    idx = _samples(p)
+    for n in range(p.P + 1):
+        got = _at(plan.slice_state(0, n), idx)
+        assert rel_l2(got, ms.iterate_points(p.K, n, idx)) <= FP64_TOL, n
 
 
 def test_full_size_c3_mixed(pr):
