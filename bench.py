@@ -198,6 +198,36 @@ def main():
             "tau_c_over_tau_f_fp64_serial": round(tau, 4),
             "S_bound_eq_speedup": round(costmodel.speedup_bound(p.P, p.K, p.nc / p.nf, tau), 3),
         }
+        # G on the grid coarsened by 2 (restriction, Euler steps with h = 2/n,
+        # linear or cubic interpolation), with the smallest power-of-two coarse
+        # count that the coarsened grid keeps stable
+        ref64 = ufine if not mixed else ufine64.copy_(ufine)
+        plan_k0 = pr.Plan([W.Problem(**{**p.__dict__, "K": 0})], mode)
+        g_slice_plain = timed(lambda: plan_k0.solve([u0], uT=[uT], want_log=False), reps=5, warm=1) / p.P
+        del plan_k0
+        f_slice = t_serial / p.P
+        coarsened = {}
+        for label, extra_flags in (("linear", W.COARSEN_G), ("cubic", W.COARSEN_G | W.CUBIC_INTERP)):
+            q = W.Problem(**dict(p.__dict__))
+            q.flags = (q.flags | extra_flags) & ~W.SKIP_CONVERGED
+            half = [v // 2 for v in q.n]
+            q.nt_coarse = W.stable_coarse_steps(half, q.a, q.nu0, q.nu_amp, q.T, q.P, power_of_two=True,
+                                                minimum=q.P)
+            plan_c = pr.Plan([q], mode)
+            t_c = timed(lambda: plan_c.solve([u0], uT=[uT], want_log=False), reps=5, warm=1)
+            _, lg_c = plan_c.solve([u0], uT=[uT], ref=[ref64])
+            del plan_c
+            qk0 = W.Problem(**{**q.__dict__, "K": 0})
+            plan_c0 = pr.Plan([qk0], mode)
+            g_slice = timed(lambda: plan_c0.solve([u0], uT=[uT], want_log=False), reps=5, warm=1) / q.P
+            del plan_c0
+            r = g_slice / f_slice
+            coarsened[label] = {
+                "nt_coarse": q.nt_coarse, "time_to_solution_ms": round(t_c, 3),
+                "G_over_F_per_slice": round(r, 4),
+                "S_bound_eq_speedup": round(1.0 / ((1 + q.K / q.P) * r + q.K / q.P), 3),
+                "defect_dk": [float("%.3e" % (lg_c[0, k, 8] / lg_c[0, k, 9])) for k in range(q.K)]}
+        extra["coarsened_G"] = {"plain_G_over_F_per_slice": round(g_slice_plain / f_slice, 4), **coarsened}
         log("comparisons", extra)
         if args.mixed_config:
             # batched FP32-sweep Parareal against plain per-slice FP64 Parareal on

@@ -38,67 +38,94 @@ __global__ void __launch_bounds__(kXferThreads) restrict_kernel(const ItemDesc *
     }
 }
 
-// Taps of fine index i on a coarse axis of nc points: even i copies point
-// i/2; odd i uses its two coarse neighbours (ORDER 1: 1/2, 1/2) or four
-// (ORDER 3: -1/16, 9/16, 9/16, -1/16), indices periodic.
-template <int ORDER, typename T>
-__device__ __forceinline__ int taps(int i, int nc, int (&idx)[4], T (&w)[4])
-{
-    if ((i & 1) == 0) {
-        idx[0] = i >> 1;
-        w[0] = (T)1;
-        return 1;
-    }
-    const int m = (i - 1) >> 1;
-    if constexpr (ORDER == 1) {
-        idx[0] = m;
-        idx[1] = wrapc(m + 1, nc);
-        w[0] = (T)0.5;
-        w[1] = (T)0.5;
-        return 2;
-    } else {
-        idx[0] = wrapc(m - 1, nc);
-        idx[1] = m;
-        idx[2] = wrapc(m + 1, nc);
-        idx[3] = wrapc(m + 2, nc);
-        w[0] = (T)(-1.0 / 16.0);
-        w[1] = (T)(9.0 / 16.0);
-        w[2] = (T)(9.0 / 16.0);
-        w[3] = (T)(-1.0 / 16.0);
-        return 4;
-    }
-}
+// Interpolation, one thread per coarse cell (x, y, z): it writes the 8 fine
+// points (2x+px, 2y+py, 2z+pz), px, py, pz in {0, 1}.  Per direction an even
+// fine index copies the coarse point, an odd one takes coarse offsets 0, 1
+// with weights 1/2, 1/2 (ORDER 1) or offsets -1, 0, 1, 2 with -1/16, 9/16,
+// 9/16, -1/16 (ORDER 3), periodic.  A fine value is the tensor-product sum
+// of the terms (wz*wy*wx) * value, z taps outermost, then y, then x, added
+// in that order (the weight products are exact).
+template <int ORDER>
+struct Taps;
+template <>
+struct Taps<1> {
+    static constexpr int lo = 0, n = 2;   // coarse offsets lo .. lo+n-1 around the cell
+    template <typename T>
+    __device__ static constexpr T w(int k) { return (T)0.5; }
+};
+template <>
+struct Taps<3> {
+    static constexpr int lo = -1, n = 4;
+    template <typename T>
+    __device__ static constexpr T w(int k) { return (k == 0 || k == 3) ? (T)(-1.0 / 16.0) : (T)(9.0 / 16.0); }
+};
 
-// Tensor-product interpolation: terms (wz*wy*wx) * value, z taps outermost,
-// then y, then x, added in that order (the weight products are exact).
 template <typename T, int ORDER>
 __global__ void __launch_bounds__(kXferThreads) prolong_kernel(const ItemDesc *__restrict__ items)
 {
+    using TP = Taps<ORDER>;
+    constexpr int NO = TP::n;
     const ItemDesc &it = items[blockIdx.y];
     const int nx = it.nx, ny = it.ny, nz = it.nz;
     const int cx = nx / 2, cy = ny / 2, cz = nz / 2;
-    const int64_t n = (int64_t)nx * ny * nz;
+    const int64_t nc = (int64_t)cx * cy * cz;
     const PR_GLOBAL T *src = (const PR_GLOBAL T *)it.src0;
     PR_GLOBAL T *dst = (PR_GLOBAL T *)it.dst;
-    for (int64_t i = (int64_t)blockIdx.x * kXferThreads + threadIdx.x; i < n;
+    for (int64_t i = (int64_t)blockIdx.x * kXferThreads + threadIdx.x; i < nc;
          i += (int64_t)gridDim.x * kXferThreads) {
-        const int x = (int)(i % nx);
-        const int64_t r = i / nx;
-        const int y = (int)(r % ny);
-        const int z = (int)(r / ny);
-        int iz[4], iy[4], ix[4];
-        T wz[4], wy[4], wx[4];
-        const int tz = taps<ORDER>(z, cz, iz, wz);
-        const int ty = taps<ORDER>(y, cy, iy, wy);
-        const int tx = taps<ORDER>(x, cx, ix, wx);
-        T acc = (T)0;
-        for (int c = 0; c < tz; ++c)
-            for (int b = 0; b < ty; ++b) {
-                const PR_GLOBAL T *row = src + ((int64_t)iz[c] * cy + iy[b]) * cx;
-                const T wzy = wz[c] * wy[b];
-                for (int a = 0; a < tx; ++a) acc = acc + (wzy * wx[a]) * row[ix[a]];
+        const int x = (int)(i % cx);
+        const int64_t r = i / cx;
+        const int y = (int)(r % cy);
+        const int z = (int)(r / cy);
+        int ox[NO], oy[NO], oz[NO];
+#pragma unroll
+        for (int k = 0; k < NO; ++k) {
+            ox[k] = wrapc(x + TP::lo + k, cx);
+            oy[k] = wrapc(y + TP::lo + k, cy);
+            oz[k] = wrapc(z + TP::lo + k, cz);
+        }
+        T v[NO][NO][NO];
+#pragma unroll
+        for (int c = 0; c < NO; ++c)
+#pragma unroll
+            for (int b = 0; b < NO; ++b) {
+                const PR_GLOBAL T *row = src + ((int64_t)oz[c] * cy + oy[b]) * cx;
+#pragma unroll
+                for (int a = 0; a < NO; ++a) v[c][b][a] = row[ox[a]];
             }
-        dst[i] = acc;
+        constexpr int E = -TP::lo;   // offset index of the cell's own coarse point
+        T out[2][2][2];
+#pragma unroll
+        for (int pz = 0; pz < 2; ++pz)
+#pragma unroll
+            for (int py = 0; py < 2; ++py)
+#pragma unroll
+                for (int px = 0; px < 2; ++px) {
+                    const int nzt = pz ? NO : 1, nyt = py ? NO : 1, nxt = px ? NO : 1;
+                    T acc = (T)0;
+#pragma unroll
+                    for (int c = 0; c < nzt; ++c)
+#pragma unroll
+                        for (int b = 0; b < nyt; ++b) {
+                            const T wz = pz ? TP::template w<T>(c) : (T)1;
+                            const T wy = py ? TP::template w<T>(b) : (T)1;
+                            const T wzy = wz * wy;
+#pragma unroll
+                            for (int a = 0; a < nxt; ++a) {
+                                const T wx = px ? TP::template w<T>(a) : (T)1;
+                                acc = acc + (wzy * wx) * v[pz ? c : E][py ? b : E][px ? a : E];
+                            }
+                        }
+                    out[pz][py][px] = acc;
+                }
+#pragma unroll
+        for (int pz = 0; pz < 2; ++pz)
+#pragma unroll
+            for (int py = 0; py < 2; ++py) {
+                PR_GLOBAL T *row = dst + ((int64_t)(2 * z + pz) * ny + (2 * y + py)) * nx + 2 * x;
+                row[0] = out[pz][py][0];
+                row[1] = out[pz][py][1];
+            }
     }
 }
 
