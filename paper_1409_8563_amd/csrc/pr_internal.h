@@ -43,8 +43,8 @@ struct PointItem {
     int64_t npts;
 };
 
-constexpr int kNormBlocks = 256;   // blocks per item of the deterministic reductions
-constexpr int kNormThreads = 256;
+constexpr int kNormBlocks = 512;   // blocks per item of the deterministic reductions
+constexpr int kNormThreads = 512;
 
 // ---- launch wrappers (kernels.hip) ----------------------------------------
 // Fine RK4, one step per launch, over the first `nitems` items of `items`
