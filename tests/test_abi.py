@@ -120,6 +120,12 @@ def test_sweep_validation_without_device():
     bad = W.small_problem(n=(4, 16, 16), order=4)
     assert _sweep_rc(bad) == L.PR_EINVAL
     assert "n[0]" in L.last_error()
+    # the largest field a kernel can index with 32-bit point offsets: 2^31 - 1 points
+    bad = W.small_problem(n=(1291, 1291, 1291))
+    assert _sweep_rc(bad) == L.PR_EINVAL and "2^31" in L.last_error()
+    ok = W.small_problem(n=(1024, 1024, 1024))
+    ok.flags |= W.ALLOW_UNSTABLE
+    assert _sweep_rc(ok) in (L.PR_EDEVICE, L.PR_ENOMEM)
 
 
 def test_plan_validation():
