@@ -263,13 +263,29 @@ int pr_kernel_variant_info(int32_t which, int32_t variant, int32_t *dtype, int32
 
 /*
  * pr_autotune -- time the fused variants of F (which = 0) or G (which = 1)
- * for this problem on the device and remember the fastest for (grid, dtype,
- * fine_order); scratch buffers come from `ws` (pr_autotune_workspace_bytes).
- * Blocking.  best_variant (HOST, may be NULL) receives the choice.
+ * for this problem and batch on the device, each with z chunks sized for 1,
+ * 2 and 4 blocks per compute unit, and remember the fastest pair for (grid,
+ * dtype, fine_order, batch); sweeps of that shape then use it (the entry of
+ * their batch, else any tuned batch of the shape).  Scratch buffers come
+ * from `ws` (pr_autotune_workspace_bytes).  Blocking.  best_variant (HOST,
+ * may be NULL) receives the variant.  Results do not depend on the choice.
  */
 size_t pr_autotune_workspace_bytes(const pr_problem *prob, int32_t dtype, int32_t batch);
 int pr_autotune(const pr_problem *prob, int32_t dtype, int32_t batch, int32_t which, void *ws,
                 size_t ws_bytes, void *stream, int32_t *best_variant);
+
+/*
+ * pr_plan_autotune -- tune the plan's own launches: every fused variant of F
+ * that applies to all instances, with z chunks sized for 1, 2 and 4 blocks
+ * per compute unit, timed on the batched F launch over all slices of all
+ * instances; likewise G on the coarse chain's launch.  The plan keeps the
+ * fastest (a recorded graph is re-recorded at the next solve).  Overwrites
+ * the slice states in the workspace (the next solve starts from u0 anyway);
+ * blocking.  Outputs (HOST, may be NULL): the chosen variants and blocks per
+ * compute unit.  Results of later solves are bitwise the same as before.
+ */
+int pr_plan_autotune(pr_plan *plan, void *stream, int32_t *fine_variant, int32_t *fine_blocks_per_cu,
+                     int32_t *coarse_variant, int32_t *coarse_blocks_per_cu);
 
 #ifdef __cplusplus
 }

@@ -215,6 +215,14 @@ class Plan:
             log = log[:, :K]
         return uT, log
 
+    def autotune(self, stream=None):
+        """Tune the plan's F and G launches (variant, blocks per CU); returns
+        {"fine": (name, bpc), "coarse": (name, bpc)}.  Blocking."""
+        vals = [ctypes.c_int32() for _ in range(4)]
+        check(lib().pr_plan_autotune(self._h, _stream_ptr(stream), *[ctypes.byref(v) for v in vals]))
+        return {"fine": (lib().pr_kernel_variant_name(0, vals[0].value).decode(), vals[1].value),
+                "coarse": (lib().pr_kernel_variant_name(1, vals[2].value).decode(), vals[3].value)}
+
     def iterations(self):
         return lib().pr_plan_iterations(self._h)
 

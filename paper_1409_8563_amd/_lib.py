@@ -23,8 +23,8 @@ EXPORTS = ["pr_last_error", "pr_version", "pr_check_stability", "pr_fine_sweep",
            "pr_plan_workspace_bytes", "pr_plan_create", "pr_plan_destroy", "pr_parareal_solve",
            "pr_plan_iterations", "pr_plan_kernel_variants", "pr_plan_timings", "pr_plan_slice_state", "pr_set_kernel_variant",
            "pr_kernel_variant_count", "pr_kernel_variant_name", "pr_kernel_variant_info",
-           "pr_autotune_workspace_bytes", "pr_autotune", "pr_transfer_workspace_bytes", "pr_restrict",
-           "pr_prolong"]
+           "pr_autotune_workspace_bytes", "pr_autotune", "pr_plan_autotune", "pr_transfer_workspace_bytes",
+           "pr_restrict", "pr_prolong"]
 
 
 class PrError(RuntimeError):
@@ -90,6 +90,7 @@ def lib():
     L.pr_autotune_workspace_bytes.argtypes = [pp, _i32, _i32]
     L.pr_autotune_workspace_bytes.restype = _sz
     L.pr_autotune.argtypes = [pp, _i32, _i32, _i32, _vp, _sz, _vp, ip]
+    L.pr_plan_autotune.argtypes = [_vp, _vp, ip, ip, ip, ip]
     L.pr_transfer_workspace_bytes.argtypes = [_i32]
     L.pr_transfer_workspace_bytes.restype = _sz
     L.pr_restrict.argtypes = [pp, _i32, _i32, _vp, _vp, _vp, _sz, _vp]

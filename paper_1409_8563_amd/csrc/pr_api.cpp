@@ -48,8 +48,34 @@ int fail(int code, const char *fmt, ...)
     } while (0)
 
 int g_fine_forced = 0, g_coarse_forced = 0;
+int g_bpc_forced = 0;   // blocks-per-CU target forced while tuning (0: tuned or default)
+
+// A kernel choice: fused variant and the launch-size target of the tile
+// layout (blocks per CU, which sets the z-chunk depth; 0 = default).
+struct Choice {
+    int v = 0;
+    int bpc = 0;
+};
 std::mutex g_tune_mu;
-std::map<std::tuple<int, int, int, int, int, int>, int> g_tuned;  // (which, nx, ny, nz, dtype, order) -> variant
+// (which, nx, ny, nz, dtype, order, batch) -> choice of the tuner
+std::map<std::tuple<int, int, int, int, int, int, int>, Choice> g_tuned;
+
+// Tuned choice for a shape: the entry of this batch, else any batch of the shape.
+bool tuned_choice(int which, const pr_problem &p, int dtype, int order, int batch, Choice *c)
+{
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    auto it = g_tuned.find({which, p.n[0], p.n[1], p.n[2], dtype, order, batch});
+    if (it == g_tuned.end()) {
+        it = g_tuned.lower_bound({which, p.n[0], p.n[1], p.n[2], dtype, order, 0});
+        if (it == g_tuned.end()) return false;
+        const auto &k = it->first;
+        if (std::get<0>(k) != which || std::get<1>(k) != p.n[0] || std::get<2>(k) != p.n[1] ||
+            std::get<3>(k) != p.n[2] || std::get<4>(k) != dtype || std::get<5>(k) != order)
+            return false;
+    }
+    *c = it->second;
+    return true;
+}
 
 int g_num_cus = 0;
 
@@ -261,15 +287,17 @@ int pick_fine_default(const pr_problem &p, int dtype)
     return find_fine(name);
 }
 
-int pick_fine(const pr_problem &p, int dtype)
+Choice pick_fine(const pr_problem &p, int dtype, int batch)
 {
-    if (g_fine_forced) return g_fine_forced;
-    {
-        std::lock_guard<std::mutex> lk(g_tune_mu);
-        auto it = g_tuned.find({0, p.n[0], p.n[1], p.n[2], dtype, p.fine_order});
-        if (it != g_tuned.end()) return it->second;
+    Choice c;
+    if (g_fine_forced) {
+        c.v = g_fine_forced;
+        c.bpc = g_bpc_forced;
+        return c;
     }
-    return pick_fine_default(p, dtype);
+    if (tuned_choice(0, p, dtype, p.fine_order, batch, &c)) return c;
+    c.v = pick_fine_default(p, dtype);
+    return c;
 }
 
 int pick_coarse_default(const pr_problem &p, int dtype)
@@ -290,15 +318,17 @@ int pick_coarse_default(const pr_problem &p, int dtype)
     return find_coarse(name);
 }
 
-int pick_coarse(const pr_problem &p, int dtype)
+Choice pick_coarse(const pr_problem &p, int dtype, int batch)
 {
-    if (g_coarse_forced) return g_coarse_forced;
-    {
-        std::lock_guard<std::mutex> lk(g_tune_mu);
-        auto it = g_tuned.find({1, p.n[0], p.n[1], p.n[2], dtype, 0});
-        if (it != g_tuned.end()) return it->second;
+    Choice c;
+    if (g_coarse_forced) {
+        c.v = g_coarse_forced;
+        c.bpc = g_bpc_forced;
+        return c;
     }
-    return pick_coarse_default(p, dtype);
+    if (tuned_choice(1, p, dtype, 0, batch, &c)) return c;
+    c.v = pick_coarse_default(p, dtype);
+    return c;
 }
 
 constexpr int kRefThreads = 256;
@@ -324,13 +354,13 @@ void fill_item(ItemDesc &it, const pr_problem &p, bool fine)
 // item order.  Returns the total number of blocks.
 int g_blocks_per_cu = 0;  // launch-size target of the tile layout (0: default)
 
-int layout(std::vector<ItemDesc> &items, const VariantInfo *vi, bool ref, int zmin)
+int layout(std::vector<ItemDesc> &items, const VariantInfo *vi, bool ref, int zmin, int bpc = 0)
 {
     if (g_blocks_per_cu == 0) {
         const char *e = getenv("PR_BLOCKS_PER_CU");
         g_blocks_per_cu = e ? std::max(1, atoi(e)) : 1;
     }
-    const int target = g_blocks_per_cu * std::max(g_num_cus, 1);
+    const int target = (bpc > 0 ? bpc : g_blocks_per_cu) * std::max(g_num_cus, 1);
     if (ref) {
         int b = 0;
         for (auto &it : items) {
@@ -397,7 +427,8 @@ int sweep_common(const pr_problem *prob_in, int dtype, int batch, const void *u_
     if (a < o + bytes && o < a + bytes) return fail(PR_EINVAL, "u_in and u_out overlap");
     rc = stability_guard(*prob, fine, !fine);
     if (rc) return rc;
-    int v = fine ? pick_fine(*prob, dtype) : pick_coarse(*prob, dtype);
+    const Choice ch = fine ? pick_fine(*prob, dtype, batch) : pick_coarse(*prob, dtype, batch);
+    const int v = ch.v;
     if (v < 1) return fail(PR_EUNSUPPORTED, "no kernel variant for this problem");
     if (fine ? !fine_applicable(v, dtype, prob->fine_order, *prob) : !coarse_applicable(v, dtype, *prob))
         return fail(PR_EUNSUPPORTED, "selected kernel variant %d does not apply to this dtype/order/n_x", v);
@@ -430,7 +461,7 @@ int sweep_common(const pr_problem *prob_in, int dtype, int batch, const void *u_
     }
     const VariantInfo *vi = fine ? fine_info(v) : coarse_info(v);
     const int zmin = fine ? 8 : 4;
-    const int nblocks = layout(items, vi, ref, zmin);
+    const int nblocks = layout(items, vi, ref, zmin, ch.bpc);
     HIPCHK(pr::launch_write_items(items.data(), batch, table, s));
     if (fine) {
         for (int j = 0; j < nsteps; ++j)
@@ -456,6 +487,7 @@ struct pr_plan {
     int K = 0;
     uint32_t flags = 0;
     int fine_v = 0, coarse_v = 0;
+    int fine_bpc = 0, coarse_bpc = 0;   // blocks-per-CU targets of the layouts (0: default)
     bool mixed = false, per_slice = false, graph = false, timed = false, skip = false, early = false;
     std::vector<pr_problem> probs;
     int Pmax = 0;
@@ -669,7 +701,7 @@ int build_tables(pr_plan *pl)
             for (int n = (pl->skip ? k : 0); n < pl->inst[i].P; ++n) items.push_back(fine_item(i, n));
         std::stable_sort(items.begin(), items.end(),
                          [](const ItemDesc &a, const ItemDesc &b) { return a.nsteps > b.nsteps; });
-        const int nb = layout(items, fvi, fref, 8);
+        const int nb = layout(items, fvi, fref, 8, pl->fine_bpc);
         (void)nb;
         int maxsteps = items.empty() ? 0 : items[0].nsteps;
         std::vector<int> act(maxsteps, 0);
@@ -690,6 +722,7 @@ int build_tables(pr_plan *pl)
     // per-slice tables: every (i, n) laid out on its own
     std::vector<ItemDesc> sl;
     pl->slice_index.assign(pl->sumP, 0);
+    pl->slice_blocks.clear();
     for (int i = 0; i < ninst; ++i)
         for (int n = 0; n < pl->inst[i].P; ++n) {
             std::vector<ItemDesc> one{fine_item(i, n)};
@@ -743,7 +776,7 @@ int build_tables(pr_plan *pl)
             }
             std::stable_sort(items.begin(), items.end(),
                              [](const ItemDesc &a, const ItemDesc &b) { return a.nsteps > b.nsteps; });
-            const int nb = layout(items, cvi, cref, 4);
+            const int nb = layout(items, cvi, cref, 4, pl->coarse_bpc);
             pl->coarse_blocks[par * Pmax + n] = nb;
             pl->coarse_cnt[n] = (int)items.size();
             pl->coarse_nch[n] = items.empty() ? 0 : (items[0].nsteps + S - 1) / S;
@@ -1127,7 +1160,10 @@ int pr_plan_create(const pr_problem *probs, int32_t ninst, int32_t mode, void *w
 
     // one fused variant for all instances: the choice for instance 0 if it
     // applies to every instance, else the generic one-point-per-thread layout
-    int fv = pick_fine(probs[0], pl->dtype), cv = pick_coarse(coarse_grid(probs[0]), pl->dtype);
+    int sumP0 = 0;
+    for (int i = 0; i < ninst; ++i) sumP0 += probs[i].P;
+    const Choice fch = pick_fine(probs[0], pl->dtype, sumP0), cch = pick_coarse(coarse_grid(probs[0]), pl->dtype, ninst);
+    int fv = fch.v, cv = cch.v;
     bool fok = fv >= 1, cok = cv >= 1;
     for (int i = 0; i < ninst; ++i) {
         fok = fok && fine_applicable(fv, pl->dtype, probs[i].fine_order, probs[i]);
@@ -1156,6 +1192,8 @@ int pr_plan_create(const pr_problem *probs, int32_t ninst, int32_t mode, void *w
     }
     pl->fine_v = fv;
     pl->coarse_v = cv;
+    pl->fine_bpc = fok ? fch.bpc : 0;
+    pl->coarse_bpc = cok ? cch.bpc : 0;
 
     plan_layout(probs, ninst, mode, (char *)ws, pl);
     rc = build_tables(pl);
@@ -1431,47 +1469,170 @@ int pr_autotune(const pr_problem *prob, int32_t dtype, int32_t batch, int32_t wh
     HIPCHK(hipMemsetAsync(a, 0, states, s));
     pr_problem p = *prob;
     p.flags |= PR_ALLOW_UNSTABLE;  // zeros stay zeros; timing only
+    p.flags &= ~(PR_COARSEN_G | PR_CUBIC_INTERP);
     std::vector<int64_t> st(batch, 0);
-    const int saved_f = g_fine_forced, saved_c = g_coarse_forced;
+    const int saved_f = g_fine_forced, saved_c = g_coarse_forced, saved_b = g_bpc_forced;
     hipEvent_t e0, e1;
     HIPCHK(hipEventCreate(&e0));
     HIPCHK(hipEventCreate(&e1));
     float best = 1e30f;
-    int bestv = -1;
+    Choice bestc;
     const int nv = which == 0 ? pr::fine_variant_count() : pr::coarse_variant_count();
-    for (int v = 2; v < nv; ++v) {
+    static const int kBpc[] = {1, 2, 4};
+    for (int v = 2; v < nv && rc == PR_OK; ++v) {
         const bool ok = which == 0 ? fine_applicable(v, dtype, p.fine_order, p) : coarse_applicable(v, dtype, p);
         if (!ok) continue;
-        if (which == 0) g_fine_forced = v;
-        else g_coarse_forced = v;
-        const int steps = which == 0 ? 6 : 8 * coarse_steps_per_launch(v);
-        rc = sweep_common(&p, dtype, batch, a, b, st.data(), which == 0 ? 2 : 2 * coarse_steps_per_launch(v), w, wsb, s,
-                          which == 0);
-        if (rc) break;
-        (void)hipEventRecord(e0, s);
-        rc = sweep_common(&p, dtype, batch, a, b, st.data(), steps, w, wsb, s, which == 0);
-        (void)hipEventRecord(e1, s);
-        if (rc) break;
-        (void)hipEventSynchronize(e1);
-        float ms = 0;
-        (void)hipEventElapsedTime(&ms, e0, e1);
-        const float per = ms / steps;
-        if (per < best) {
-            best = per;
-            bestv = v;
+        for (int bpc : kBpc) {
+            if (which == 0) g_fine_forced = v;
+            else g_coarse_forced = v;
+            g_bpc_forced = bpc;
+            const int steps = which == 0 ? 6 : 8 * coarse_steps_per_launch(v);
+            rc = sweep_common(&p, dtype, batch, a, b, st.data(), which == 0 ? 2 : 2 * coarse_steps_per_launch(v), w,
+                              wsb, s, which == 0);
+            if (rc) break;
+            (void)hipEventRecord(e0, s);
+            rc = sweep_common(&p, dtype, batch, a, b, st.data(), steps, w, wsb, s, which == 0);
+            (void)hipEventRecord(e1, s);
+            if (rc) break;
+            (void)hipEventSynchronize(e1);
+            float ms = 0;
+            (void)hipEventElapsedTime(&ms, e0, e1);
+            const float per = ms / steps;
+            if (per < best) {
+                best = per;
+                bestc.v = v;
+                bestc.bpc = bpc;
+            }
         }
     }
     g_fine_forced = saved_f;
     g_coarse_forced = saved_c;
+    g_bpc_forced = saved_b;
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
     if (rc) return rc;
-    if (bestv < 0) return fail(PR_EUNSUPPORTED, "no fused variant applies");
+    if (bestc.v < 2) return fail(PR_EUNSUPPORTED, "no fused variant applies");
     {
         std::lock_guard<std::mutex> lk(g_tune_mu);
-        g_tuned[{which, p.n[0], p.n[1], p.n[2], dtype, which == 0 ? p.fine_order : 0}] = bestv;
+        g_tuned[{which, p.n[0], p.n[1], p.n[2], dtype, which == 0 ? p.fine_order : 0, batch}] = bestc;
     }
-    if (best_variant) *best_variant = bestv;
+    if (best_variant) *best_variant = bestc.v;
+    return PR_OK;
+}
+
+int pr_plan_autotune(pr_plan *pl, void *stream, int32_t *fine_variant, int32_t *fine_blocks_per_cu,
+                     int32_t *coarse_variant, int32_t *coarse_blocks_per_cu)
+{
+    if (!pl) return fail(PR_EINVAL, "plan is NULL");
+    int rc = device_ready();
+    if (rc) return rc;
+    hipStream_t s = (hipStream_t)stream;
+    const size_t es = esize(pl->dtype);
+    // zero the sweep inputs of every slice and the coarse inputs: the timed
+    // launches read them (times do not depend on the values)
+    for (const auto &in : pl->inst) {
+        HIPCHK(hipMemsetAsync(in.Ulo, 0, (size_t)(in.P + 1) * in.npts * es, s));
+        if (in.Cin) HIPCHK(hipMemsetAsync(in.Cin, 0, (size_t)in.npts / 8 * es, s));
+    }
+    HIPCHK(hipStreamSynchronize(s));
+    hipEvent_t e0, e1;
+    HIPCHK(hipEventCreate(&e0));
+    HIPCHK(hipEventCreate(&e1));
+    static const int kBpc[] = {1, 2, 4};
+    const int saved[4] = {pl->fine_v, pl->fine_bpc, pl->coarse_v, pl->coarse_bpc};
+    auto applies = [&](int which, int v) {
+        for (const auto &p : pl->probs) {
+            const bool ok = which == 0 ? fine_applicable(v, pl->dtype, p.fine_order, p)
+                                       : coarse_applicable(v, pl->dtype, coarse_grid(p));
+            if (!ok) return false;
+        }
+        return true;
+    };
+    // time one F step launch over all slices (iteration 0 table), and one
+    // chunk of the coarse chain (slice 0 table), per candidate
+    auto time_one = [&](int which, float *ms_out) -> int {
+        int r = build_tables(pl);
+        if (r) return r;
+        for (int rep = 0; rep < 2; ++rep) {
+            if (rep == 1) HIPCHK(hipEventRecord(e0, s));
+            for (int t = 0; t < 3; ++t) {
+                if (which == 0) {
+                    if (pl->fine_active_blocks.empty() || pl->fine_active_blocks[0].empty()) break;
+                    HIPCHK(pr::launch_fine_step(pl->fine_v, pl->dtype, pl->probs[0].fine_order,
+                                                pl->fine_tab + pl->fine_off[0], pl->fine_cnt[0],
+                                                pl->fine_active_blocks[0][0], 0, s));
+                } else {
+                    if (pl->coarse_cnt.empty() || !pl->coarse_cnt[0]) break;
+                    HIPCHK(pr::launch_coarse_chunk(pl->coarse_v, pl->dtype, pl->coarse_tab, pl->coarse_cnt[0],
+                                                   pl->coarse_blocks[0], 0, s));
+                }
+            }
+        }
+        HIPCHK(hipEventRecord(e1, s));
+        HIPCHK(hipEventSynchronize(e1));
+        float ms = 0;
+        HIPCHK(hipEventElapsedTime(&ms, e0, e1));
+        *ms_out = ms;
+        return PR_OK;
+    };
+    Choice bestf{saved[0], saved[1]}, bestg{saved[2], saved[3]};
+    for (int which = 0; which < 2 && rc == PR_OK; ++which) {
+        if (which == 0 && pl->K == 0) continue;   // no fine sweep in the solve
+        float best = 1e30f;
+        const int nv = which == 0 ? pr::fine_variant_count() : pr::coarse_variant_count();
+        for (int v = 2; v < nv && rc == PR_OK; ++v) {
+            if (!applies(which, v)) continue;
+            const VariantInfo *vi = which == 0 ? pr::fine_variant(v) : pr::coarse_variant(v);
+            if (which == 0 && vi->order != pl->probs[0].fine_order) continue;
+            for (int bpc : kBpc) {
+                if (which == 0) {
+                    pl->fine_v = v;
+                    pl->fine_bpc = bpc;
+                } else {
+                    pl->coarse_v = v;
+                    pl->coarse_bpc = bpc;
+                }
+                float ms = 0;
+                rc = time_one(which, &ms);
+                if (rc) break;
+                if (ms < best) {
+                    best = ms;
+                    (which == 0 ? bestf : bestg) = Choice{v, bpc};
+                }
+            }
+        }
+        if (which == 0) {
+            pl->fine_v = bestf.v;
+            pl->fine_bpc = bestf.bpc;
+        } else {
+            pl->coarse_v = bestg.v;
+            pl->coarse_bpc = bestg.bpc;
+        }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (rc) {
+        pl->fine_v = saved[0];
+        pl->fine_bpc = saved[1];
+        pl->coarse_v = saved[2];
+        pl->coarse_bpc = saved[3];
+    }
+    int r2 = build_tables(pl);
+    if (!rc) rc = r2;
+    // a recorded graph holds the old launch shapes
+    if (pl->exec) {
+        (void)hipGraphExecDestroy(pl->exec);
+        pl->exec = nullptr;
+    }
+    if (pl->graph_h) {
+        (void)hipGraphDestroy(pl->graph_h);
+        pl->graph_h = nullptr;
+    }
+    if (rc) return rc;
+    if (fine_variant) *fine_variant = pl->fine_v;
+    if (fine_blocks_per_cu) *fine_blocks_per_cu = pl->fine_bpc;
+    if (coarse_variant) *coarse_variant = pl->coarse_v;
+    if (coarse_blocks_per_cu) *coarse_blocks_per_cu = pl->coarse_bpc;
     return PR_OK;
 }
 

@@ -256,3 +256,9 @@ def test_grid_transfer_validation_without_device():
     q = W.small_problem(n=(12, 9, 8), P=2)
     s = L.to_struct(q)
     assert L.lib().pr_restrict(ctypes.byref(s), 2, 1, 16, 16 + big, 16, 1 << 20, None) == L.PR_EINVAL
+
+
+def test_plan_autotune_validation():
+    L = _lib()
+    v = (ctypes.c_int32 * 4)()
+    assert L.lib().pr_plan_autotune(None, None, None, None, None, None) == L.PR_EINVAL

@@ -446,6 +446,28 @@ def test_nonfinite_input_is_reported(pr):
     assert e.value.code == -6
 
 
+def test_plan_autotune_keeps_results(pr):
+    """Tuning a plan's launches (variant and z-chunk depth) changes no bit of
+    the result, eager or replayed from a graph recorded before the tuning."""
+    probs, u0s = [], []
+    for i, (n, nu0) in enumerate([(32, 0.004), (48, 0.006), (40, 0.005)]):
+        p = W.small_problem(n=(n, n, n), nu0=nu0, P=4, nf=8, nc=8, K=2)
+        probs.append(p)
+        u0s.append(cuda(W.random_field(p.n, 250 + i)))
+    for mode in (pr.PR_MODE_MIXED, pr.PR_MODE_FP64 | pr.PR_MODE_GRAPH):
+        say("plan autotune mode", mode)
+        plan = pr.Plan(probs, mode)
+        before, blog = plan.solve(u0s)
+        before = [host(x) for x in before]
+        choice = plan.autotune()
+        assert choice["fine"][1] in (1, 2, 4) and choice["coarse"][1] in (1, 2, 4)
+        for rep in range(2):
+            after, alog = plan.solve(u0s)
+            for i in range(len(probs)):
+                assert np.array_equal(host(after[i]), before[i]), (mode, rep, i)
+            assert np.array_equal(alog, blog)
+
+
 def test_autotune_keeps_results(pr):
     import torch
     p = W.small_problem(n=(64, 64, 64), nu0=0.002, P=2, nf=50, nc=50)
@@ -574,7 +596,10 @@ def test_full_size_c4_batched(pr):
     probs = [p for p, _ in insts]
     say("c4 batched: %d instances" % len(probs))
     u0s = [cuda(W.synth_u0(p.n, m)) for p, m in insts]
-    plan = pr.Plan(probs, pr.PR_MODE_MIXED)
+    # one F launch per step over all slices of all instances, tuned tiles and
+    # z chunks, the whole solve replayed from a recorded graph
+    plan = pr.Plan(probs, pr.PR_MODE_MIXED | pr.PR_MODE_GRAPH)
+    say("c4 tuned", plan.autotune())
     uT, log = plan.solve(u0s)
     for i, (p, m) in enumerate(insts):
         idx = _samples(p, count=1024, seed=i)
