@@ -1548,14 +1548,17 @@ int pr_plan_autotune(pr_plan *pl, void *stream, int32_t *fine_variant, int32_t *
         }
         return true;
     };
-    // time one F step launch over all slices (iteration 0 table), and one
-    // chunk of the coarse chain (slice 0 table), per candidate
+    // time F step launches over all slices (iteration 0 table), and coarse
+    // chunks of the chain (slice 0 table) covering at least 12 Euler steps;
+    // the figure compared is the time per step
     auto time_one = [&](int which, float *ms_out) -> int {
         int r = build_tables(pl);
         if (r) return r;
+        const int S = which == 0 ? 1 : coarse_steps_per_launch(pl->coarse_v);
+        const int launches = which == 0 ? 3 : std::max(3, (12 + S - 1) / S);
         for (int rep = 0; rep < 2; ++rep) {
             if (rep == 1) HIPCHK(hipEventRecord(e0, s));
-            for (int t = 0; t < 3; ++t) {
+            for (int t = 0; t < launches; ++t) {
                 if (which == 0) {
                     if (pl->fine_active_blocks.empty() || pl->fine_active_blocks[0].empty()) break;
                     HIPCHK(pr::launch_fine_step(pl->fine_v, pl->dtype, pl->probs[0].fine_order,
@@ -1572,7 +1575,7 @@ int pr_plan_autotune(pr_plan *pl, void *stream, int32_t *fine_variant, int32_t *
         HIPCHK(hipEventSynchronize(e1));
         float ms = 0;
         HIPCHK(hipEventElapsedTime(&ms, e0, e1));
-        *ms_out = ms;
+        *ms_out = ms / (float)(launches * S);
         return PR_OK;
     };
     Choice bestf{saved[0], saved[1]}, bestg{saved[2], saved[3]};
