@@ -61,6 +61,58 @@ def cpu_baseline(p, u0_np, budget_s=15.0):
                                                                                         dt)}
 
 
+def per_config_rates(pr, W, torch, kernel_of):
+    """Rate of the batched fine-step launch (all P slices in one launch) on
+    every workload, timed with HIP events over a few steps on random data
+    (outside the timed region); the batched workload runs a one-iteration
+    timed plan over its 64 instances."""
+    out = {}
+
+    def ev_time(fn, steps):
+        fn(steps)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        fn(steps)
+        e1.record()
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / steps
+
+    for name in ("c1_32_fp64", "c2_128_fp64", "c3_256_mixed", "c5_512_mixed"):
+        p, _ = W.config(name)
+        mixed = W.MIXED[name]
+        tdt = torch.float32 if mixed else torch.float64
+        es = 4 if mixed else 8
+        u = torch.randn((p.P,) + tuple(reversed(p.n)), dtype=tdt, device="cuda")
+        o = torch.empty_like(u)
+        steps = 16 if p.npts * p.P < (1 << 30) else 4
+        ms = ev_time(lambda k: pr.fine_sweep(p, u, [s * p.nf for s in range(p.P)], k, u_out=o), steps)
+        lups = p.P * p.npts
+        fv = pr.sweep_kernel_variant(p, pr.PR_FP32 if mixed else pr.PR_FP64, p.P, 0)
+        out[name] = {"glups": round(lups / ms / 1e6, 1), "gbs": round(lups * 2 * es / ms / 1e6, 1),
+                     "frac": round(lups * 2 * es / ms / 1e6 / HBM_PEAK_GBS, 4),
+                     "launch_us": round(ms * 1e3, 1), "kernel": "%s (%s)" % (kernel_of(fv), fv)}
+        del u, o
+        torch.cuda.empty_cache()
+    insts = W.batched_config(64)
+    probs = [W.Problem(**{**q.__dict__, "K": 1}) for q, _ in insts]
+    u0s = [torch.randn(tuple(reversed(q.n)), dtype=torch.float64, device="cuda") for q in probs]
+    plan = pr.Plan(probs, pr.PR_MODE_MIXED | pr.PR_MODE_TIMED)
+    plan.solve(u0s, want_log=False)
+    plan.solve(u0s, want_log=False)
+    tm = plan.timings()
+    # F launches of the plan: step j covers the slices with more than j steps
+    lups = sum(q.P * q.npts * q.nf for q in probs)
+    out["c4_batched_64"] = {"glups": round(lups / tm["fine_ms"] / 1e6, 1),
+                            "gbs": round(lups * 8 / tm["fine_ms"] / 1e6, 1),
+                            "frac": round(lups * 8 / tm["fine_ms"] / 1e6 / HBM_PEAK_GBS, 4),
+                            "fine_launches": int(tm["fine_launches"]),
+                            "kernel": "%s (%s)" % (kernel_of(plan.kernel_variants()[0]), plan.kernel_variants()[0])}
+    del plan, u0s
+    torch.cuda.empty_cache()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -71,6 +123,8 @@ def main():
     ap.add_argument("--no-compare", action="store_true")
     ap.add_argument("--mixed-config", default="c3_256_mixed",
                     help="workload of the batched-FP32 vs plain-per-slice-FP64 comparison ('' to skip)")
+    ap.add_argument("--no-per-config", action="store_true",
+                    help="skip the per-workload F kernel rates (all five workloads)")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="run one plain device-to-device copy of this size first (calibrates HBM counters)")
     args = ap.parse_args()
@@ -264,6 +318,10 @@ def main():
             del um, u_fine64, uT_mixed, uT_plain
             torch.cuda.empty_cache()
             log("mixed comparison", extra["mixed_vs_plain_fp64"])
+
+    if not args.no_per_config:
+        extra["per_config_fine_kernel"] = per_config_rates(pr, W, torch, kernel_of)
+        log("per-config F rates", extra["per_config_fine_kernel"])
 
     cpu = None
     if not args.no_cpu_baseline:

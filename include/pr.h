@@ -261,6 +261,11 @@ const char *pr_kernel_variant_name(int32_t which, int32_t variant);
 int pr_kernel_variant_info(int32_t which, int32_t variant, int32_t *dtype, int32_t *order, int32_t *tile_x,
                            int32_t *tile_y, int32_t *nxp, int32_t *steps, int32_t *nx_exact);
 
+/* Variant a sweep of this problem, dtype and batch would launch for F
+ * (which = 0) or G (which = 1) -- tuned, forced or built-in default (HOST
+ * output).  No device work. */
+int pr_sweep_kernel_variant(const pr_problem *prob, int32_t dtype, int32_t batch, int32_t which, int32_t *variant);
+
 /*
  * pr_autotune -- time the fused variants of F (which = 0) or G (which = 1)
  * for this problem and batch on the device, each with z chunks sized for 1,

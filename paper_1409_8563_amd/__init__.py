@@ -17,7 +17,8 @@ from ._lib import (PR_ALLOW_UNSTABLE, PR_COARSEN_G, PR_CUBIC_INTERP, PR_EARLY_ST
                    PR_NU_FROZEN, PR_SKIP_CONVERGED, PrError, check, lib, to_struct)
 
 __all__ = ["fine_sweep", "coarse_sweep", "parareal_update", "defect_norm", "restrict", "prolong", "Plan",
-           "check_stability", "set_kernel_variant", "variants", "autotune", "PrError", "lib"]
+           "check_stability", "set_kernel_variant", "variants", "sweep_kernel_variant", "autotune", "PrError",
+           "lib"]
 
 
 def _torch():
@@ -159,6 +160,14 @@ def variants(which):
                         order=vals[1].value, tile=(vals[2].value, vals[3].value), nxp=vals[4].value,
                         steps=vals[5].value, nx_exact=vals[6].value))
     return out
+
+
+def sweep_kernel_variant(prob, dtype, batch, which):
+    """Name of the fused variant a sweep would launch (which: 0 = F, 1 = G)."""
+    s = to_struct(prob)
+    v = ctypes.c_int32()
+    check(lib().pr_sweep_kernel_variant(ctypes.byref(s), int(dtype), int(batch), int(which), ctypes.byref(v)))
+    return lib().pr_kernel_variant_name(int(which), v.value).decode()
 
 
 def autotune(prob, dtype, batch, which, stream=None):

@@ -24,7 +24,7 @@ EXPORTS = ["pr_last_error", "pr_version", "pr_check_stability", "pr_fine_sweep",
            "pr_plan_iterations", "pr_plan_kernel_variants", "pr_plan_timings", "pr_plan_slice_state", "pr_set_kernel_variant",
            "pr_kernel_variant_count", "pr_kernel_variant_name", "pr_kernel_variant_info",
            "pr_autotune_workspace_bytes", "pr_autotune", "pr_plan_autotune", "pr_transfer_workspace_bytes",
-           "pr_restrict", "pr_prolong"]
+           "pr_restrict", "pr_prolong", "pr_sweep_kernel_variant"]
 
 
 class PrError(RuntimeError):
@@ -91,6 +91,7 @@ def lib():
     L.pr_autotune_workspace_bytes.restype = _sz
     L.pr_autotune.argtypes = [pp, _i32, _i32, _i32, _vp, _sz, _vp, ip]
     L.pr_plan_autotune.argtypes = [_vp, _vp, ip, ip, ip, ip]
+    L.pr_sweep_kernel_variant.argtypes = [pp, _i32, _i32, _i32, ip]
     L.pr_transfer_workspace_bytes.argtypes = [_i32]
     L.pr_transfer_workspace_bytes.restype = _sz
     L.pr_restrict.argtypes = [pp, _i32, _i32, _vp, _vp, _vp, _sz, _vp]

@@ -1444,6 +1444,20 @@ int pr_kernel_variant_info(int32_t which, int32_t variant, int32_t *dtype, int32
     return PR_OK;
 }
 
+int pr_sweep_kernel_variant(const pr_problem *prob, int32_t dtype, int32_t batch, int32_t which, int32_t *variant)
+{
+    int rc = validate_problem(prob, false);
+    if (rc) return rc;
+    if (dtype != PR_FP32 && dtype != PR_FP64) return fail(PR_EINVAL, "dtype must be PR_FP32 or PR_FP64");
+    if (batch < 1 || (which != 0 && which != 1)) return fail(PR_EINVAL, "batch must be >= 1, which 0 or 1");
+    pr_problem p = *prob;
+    p.flags &= ~(PR_COARSEN_G | PR_CUBIC_INTERP);
+    const Choice c = which == 0 ? pick_fine(p, dtype, batch) : pick_coarse(p, dtype, batch);
+    if (c.v < 1) return fail(PR_EUNSUPPORTED, "no kernel variant for this problem");
+    if (variant) *variant = c.v;
+    return PR_OK;
+}
+
 size_t pr_autotune_workspace_bytes(const pr_problem *prob, int32_t dtype, int32_t batch)
 {
     if (validate_problem(prob, false) || batch < 1 || (dtype != PR_FP32 && dtype != PR_FP64)) return 0;
