@@ -410,6 +410,28 @@ def test_multi_instance_uneven(pr, orc):
                 assert rel_l2(uT[i], U[-1]) <= FP64_TOL
 
 
+def test_multi_instance_whole_row_kernels(pr, orc):
+    """Instances that share n_x = 128 (whole-row F and G kernels) but differ in
+    n_y, n_z, a, nu and step counts, in one FP64 plan: each instance matches
+    the oracle and its own single-instance solve bitwise."""
+    probs, u0s = [], []
+    for i, (ny, nz, a, nu0, nf, nc) in enumerate([(24, 16, (0.7, -0.4, 0.2), 0.002, 8, 8),
+                                                  (40, 12, (-0.5, 0.9, 0.3), 0.001, 10, 10)]):
+        p = W.small_problem(n=(128, ny, nz), a=a, nu0=nu0, P=3, nf=nf, nc=nc, K=2)
+        probs.append(p)
+        u0s.append(W.random_field(p.n, 260 + i))
+    plan = pr.Plan(probs, pr.PR_MODE_FP64)
+    assert plan.kernel_variants()[0].startswith("rk4w_") and plan.kernel_variants()[1].startswith("euler4w_")
+    uT, _ = plan.solve([cuda(u) for u in u0s])
+    for i, p in enumerate(probs):
+        say("whole-row multi-instance", i)
+        U, _ = orc.parareal(p, u0s[i], K=p.K)
+        got = host(uT[i])
+        assert rel_l2(got, U[-1]) <= FP64_TOL, i
+        one, _, _, _ = _solve(pr, [p], [u0s[i]], pr.PR_MODE_FP64)
+        assert np.array_equal(one[0], got), i
+
+
 def test_reference_defect_and_early_stop(pr, orc):
     import torch
     p = W.small_problem(n=(24, 24, 24), P=4, nf=6, nc=5, K=4)
