@@ -271,7 +271,8 @@ bool coarse_applicable(int v, int dtype, const pr_problem &p)
     return vi && vi->dtype == dtype && p.n[0] % vi->nxp == 0 && (vi->rowx == 0 || p.n[0] == vi->rowx);
 }
 
-int pick_fine_default(const pr_problem &p, int dtype)
+// Built-in choice (measured on the five workloads); batch = fields per launch.
+int pick_fine_default(const pr_problem &p, int dtype, int batch)
 {
     const int order = p.fine_order;
     const bool even = p.n[0] % 2 == 0;
@@ -283,7 +284,10 @@ int pick_fine_default(const pr_problem &p, int dtype)
                                : "rk4b_f64_t32x32_p1x2_d2";
     else
         name = order == 4 ? (even ? "rk4_f32_o4_t32x16_p2x2" : "rk4_f32_o4_t32x16_p1x2")
-                          : (even ? "rk4b_f32_t64x32_p2x2_d2" : "rk4b_f32_t32x32_p1x4_d2");
+               : p.n[0] == 256 ? "rk4w_f32_x256_y8_p4x2_w8"
+               : p.n[0] == 128 ? (batch >= 4 ? "rk4w_f32_x128_y16_p2x3_w8" : "rk4w_f32_x128_y8_p2x1_w16")
+               : even          ? "rk4b_f32_t64x32_p2x2_d2"
+                               : "rk4b_f32_t32x32_p1x4_d2";
     return find_fine(name);
 }
 
@@ -296,7 +300,7 @@ Choice pick_fine(const pr_problem &p, int dtype, int batch)
         return c;
     }
     if (tuned_choice(0, p, dtype, p.fine_order, batch, &c)) return c;
-    c.v = pick_fine_default(p, dtype);
+    c.v = pick_fine_default(p, dtype, batch);
     return c;
 }
 
@@ -1184,7 +1188,7 @@ int pr_plan_create(const pr_problem *probs, int32_t ninst, int32_t mode, void *w
     generic.n[0] = all_even ? 2 : 3;
     pr_problem generic_c = coarse_grid(probs[0]);
     generic_c.n[0] = all_even_c ? 2 : 3;
-    if (!fok) fv = g_fine_forced ? -1 : pick_fine_default(generic, pl->dtype);
+    if (!fok) fv = g_fine_forced ? -1 : pick_fine_default(generic, pl->dtype, sumP0);
     if (!cok) cv = g_coarse_forced ? -1 : pick_coarse_default(generic_c, pl->dtype);
     if (fv < 1 || cv < 1) {
         delete pl;

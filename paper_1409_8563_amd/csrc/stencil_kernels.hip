@@ -1049,8 +1049,11 @@ __global__ void __launch_bounds__(64 * NW)
         }
     };
 
-    auto body = [&](auto Mc, int p) {
+    // FAST: a wavefront that computes all four stages, after the pipeline
+    // fill (every stage active): straight-line code, only the store guarded.
+    auto body = [&](auto Mc, auto FASTc, int p) __attribute__((always_inline)) {
         constexpr int M = decltype(Mc)::value;
+        constexpr bool FAST = decltype(FASTc)::value;
         constexpr int WS = M & 1;        // slot written in this iteration
         constexpr int RS = (M + 1) & 1;  // slot written in the previous iteration
         __syncthreads();
@@ -1061,10 +1064,10 @@ __global__ void __launch_bounds__(64 * NW)
         load_plane(p + PD, pf[M % PD]);
         put(ic<0>{}, ic<WS>{}, ur[slot<L>(M, 0)]);
 
-        T S[NY][NXP];
-        // stage 1 at plane p - 1
-        if (act1 && p >= z0 - 2) {
-            stencil(fetch(ic<0>{}, ic<RS>{}), ur, ic<slot<L>(M, 1)>{}, ic<slot<L>(M, 2)>{}, ic<slot<L>(M, 0)>{}, w1, S);
+        // the four stage updates, each reading its in-plane neighbour rows nb
+        auto st1 = [&](const Nb &nb) __attribute__((always_inline)) {
+            T S[NY][NXP];
+            stencil(nb, ur, ic<slot<L>(M, 1)>{}, ic<slot<L>(M, 2)>{}, ic<slot<L>(M, 0)>{}, w1, S);
 #pragma unroll
             for (int iy = 0; iy < NY; ++iy)
 #pragma unroll
@@ -1074,10 +1077,10 @@ __global__ void __launch_bounds__(64 * NW)
                     ac[slot<L>(M, 1)][iy][ix] = fmaT(kc.b1, S[iy][ix], u);
                 }
             put(ic<1>{}, ic<WS>{}, y1[slot<L>(M, 1)]);
-        }
-        // stage 2 at plane p - 2
-        if (act2 && p >= z0) {
-            stencil(fetch(ic<1>{}, ic<RS>{}), y1, ic<slot<L>(M, 2)>{}, ic<slot<L>(M, 3)>{}, ic<slot<L>(M, 1)>{}, w2, S);
+        };
+        auto st2 = [&](const Nb &nb) __attribute__((always_inline)) {
+            T S[NY][NXP];
+            stencil(nb, y1, ic<slot<L>(M, 2)>{}, ic<slot<L>(M, 3)>{}, ic<slot<L>(M, 1)>{}, w2, S);
 #pragma unroll
             for (int iy = 0; iy < NY; ++iy)
 #pragma unroll
@@ -1087,10 +1090,10 @@ __global__ void __launch_bounds__(64 * NW)
                     ac[slot<L>(M, 2)][iy][ix] = fmaT(kc.b2, S[iy][ix], ac[slot<L>(M, 2)][iy][ix]);
                 }
             put(ic<2>{}, ic<WS>{}, y2[slot<L>(M, 2)]);
-        }
-        // stage 3 at plane p - 3
-        if (act3 && p >= z0 + 2) {
-            stencil(fetch(ic<2>{}, ic<RS>{}), y2, ic<slot<L>(M, 3)>{}, ic<slot<L>(M, 4)>{}, ic<slot<L>(M, 2)>{}, w2, S);
+        };
+        auto st3 = [&](const Nb &nb) __attribute__((always_inline)) {
+            T S[NY][NXP];
+            stencil(nb, y2, ic<slot<L>(M, 3)>{}, ic<slot<L>(M, 4)>{}, ic<slot<L>(M, 2)>{}, w2, S);
 #pragma unroll
             for (int iy = 0; iy < NY; ++iy)
 #pragma unroll
@@ -1100,11 +1103,10 @@ __global__ void __launch_bounds__(64 * NW)
                     ac[slot<L>(M, 3)][iy][ix] = fmaT(kc.b3, S[iy][ix], ac[slot<L>(M, 3)][iy][ix]);
                 }
             put(ic<3>{}, ic<WS>{}, y3[slot<L>(M, 3)]);
-        }
-        // stage 4 at plane p - 4, stored
-        const int q = p - 4;
-        if (act4 && p >= z0 + 4 && q < zend) {
-            stencil(fetch(ic<3>{}, ic<RS>{}), y3, ic<slot<L>(M, 4)>{}, ic<slot<L>(M, 5)>{}, ic<slot<L>(M, 3)>{}, w4, S);
+        };
+        auto st4 = [&](const Nb &nb, int q) __attribute__((always_inline)) {
+            T S[NY][NXP];
+            stencil(nb, y3, ic<slot<L>(M, 4)>{}, ic<slot<L>(M, 5)>{}, ic<slot<L>(M, 3)>{}, w4, S);
             T *obase = dst + (size_t)q * nxy;
 #pragma unroll
             for (int iy = 0; iy < NY; ++iy) {
@@ -1116,6 +1118,18 @@ __global__ void __launch_bounds__(64 * NW)
                     gst<Vec<T, NXP>>(obase + rowoff[iy], v);
                 }
             }
+        };
+        const int q = p - 4;
+        if constexpr (FAST) {
+            st1(fetch(ic<0>{}, ic<RS>{}));
+            st2(fetch(ic<1>{}, ic<RS>{}));
+            st3(fetch(ic<2>{}, ic<RS>{}));
+            if (q < zend) st4(fetch(ic<3>{}, ic<RS>{}), q);
+        } else {
+            if (act1 && p >= z0 - 2) st1(fetch(ic<0>{}, ic<RS>{}));   // stage 1 at plane p - 1
+            if (act2 && p >= z0) st2(fetch(ic<1>{}, ic<RS>{}));       // stage 2 at plane p - 2
+            if (act3 && p >= z0 + 2) st3(fetch(ic<2>{}, ic<RS>{}));   // stage 3 at plane p - 3
+            if (act4 && p >= z0 + 4 && q < zend) st4(fetch(ic<3>{}, ic<RS>{}), q);   // stage 4, stored
         }
     };
 
@@ -1123,10 +1137,21 @@ __global__ void __launch_bounds__(64 * NW)
     const int niter = (zend - z0) + 8;
 #pragma unroll
     for (int d = 0; d < PD; ++d) load_plane(pstart + d, pf[d]);
-    for (int pb = 0; pb < niter; pb += L) {
+    // trips of L iterations; the first two contain the pipeline fill (stage s
+    // starts at iteration 2s - 2 of the chunk), later ones have every stage
+    // active.  Both loops execute one barrier per iteration and the same
+    // number of trips, so wavefronts on either path meet at every barrier.
+    auto trip = [&](int pb, auto FASTc) __attribute__((always_inline)) {
         [&]<int... Ms>(std::integer_sequence<int, Ms...>) {
-            (body(ic<Ms>{}, pstart + pb + Ms), ...);
+            (body(ic<Ms>{}, FASTc, pstart + pb + Ms), ...);
         }(std::make_integer_sequence<int, L>{});
+    };
+    if (act4) {
+        int pb = 0;
+        for (; pb < niter && pb < 2 * L; pb += L) trip(pb, std::false_type{});
+        for (; pb < niter; pb += L) trip(pb, std::true_type{});
+    } else {
+        for (int pb = 0; pb < niter; pb += L) trip(pb, std::false_type{});
     }
 }
 // ---------------------------------------------------------------------------
@@ -1390,8 +1415,11 @@ __global__ void __launch_bounds__(64 * NW)
         }
     };
 
-    auto body = [&](auto Mc, int p) {
+    // FAST: a wavefront that computes every stage, after the pipeline fill:
+    // straight-line code, only the final store guarded
+    auto body = [&](auto Mc, auto FASTc, int p) __attribute__((always_inline)) {
         constexpr int M = decltype(Mc)::value;
+        constexpr bool FAST = decltype(FASTc)::value;
         constexpr int WS = M & 1, RS = (M + 1) & 1;
         __syncthreads();
 #pragma unroll
@@ -1407,7 +1435,7 @@ __global__ void __launch_bounds__(64 * NW)
                     constexpr int s = Ss + 1;          // stage s computes plane p - s from f[s-1]
                     constexpr int sc = slot<L>(M, s);
                     const bool wact = ry0 + NY - 1 >= s && ry0 < EY - s;
-                    if (wact && p >= z0 - S + 2 * s && p < zend + S) {
+                    if (FAST || (wact && p >= z0 - S + 2 * s && p < zend + S)) {
                         const Vec<T, NXP> up =
                             *reinterpret_cast<const Vec<T, NXP> *>(&lds[s - 1][RS][wup][NE - 1][cx0]);
                         const Vec<T, NXP> dn = *reinterpret_cast<const Vec<T, NXP> *>(&lds[s - 1][RS][wdn][0][cx0]);
@@ -1436,7 +1464,7 @@ __global__ void __launch_bounds__(64 * NW)
 #pragma unroll
                                 for (int ix = 0; ix < NXP; ++ix) f[s][slot<L>(M, s)][iy][ix] = res[iy][ix];
                             put(ic<s>{}, ic<WS>{}, res);
-                        } else {
+                        } else if (!FAST || p < zend + S) {
                             T *obase = dst + (size_t)(p - S) * nxy;
 #pragma unroll
                             for (int iy = 0; iy < NY; ++iy) {
@@ -1458,10 +1486,21 @@ __global__ void __launch_bounds__(64 * NW)
     const int niter = (zend - z0) + 2 * S;
 #pragma unroll
     for (int d = 0; d < PD; ++d) load_plane(pstart + d, pf[d]);
-    for (int pb = 0; pb < niter; pb += U) {
+    // trips of U iterations; stage s starts at iteration 2s - S of the chunk
+    // pipeline, so trips from pb >= 2S on have every stage active.  Both
+    // loops run one barrier per iteration and the same number of trips.
+    auto trip = [&](int pb, auto FASTc) __attribute__((always_inline)) {
         [&]<int... Ms>(std::integer_sequence<int, Ms...>) {
-            (body(ic<Ms>{}, pstart + pb + Ms), ...);
+            (body(ic<Ms>{}, FASTc, pstart + pb + Ms), ...);
         }(std::make_integer_sequence<int, U>{});
+    };
+    constexpr int kFastFrom = ((2 * S + U - 1) / U) * U;
+    if (ry0 + NY - 1 >= S && ry0 < EY - S) {
+        int pb = 0;
+        for (; pb < niter && pb < kFastFrom; pb += U) trip(pb, std::false_type{});
+        for (; pb < niter; pb += U) trip(pb, std::true_type{});
+    } else {
+        for (int pb = 0; pb < niter; pb += U) trip(pb, std::false_type{});
     }
 }
 
