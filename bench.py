@@ -25,6 +25,13 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
 
+# The paper's measured Parareal speedups (Table 1: K = 3, N_f/N_c = 16, one
+# time slice per node on Piz Daint; CPU runs on 8-core Xeon E5-2670 nodes,
+# GPU runs on one NVIDIA K20X per node).  Context only: another machine.
+PAPER_TABLE1 = {"nodes": [4, 8, 16, 32, 64, 128],
+                "S_measured_cpu": [1.3, 2.6, 5.0, 9.5, 17.6, 29.7],
+                "S_measured_gpu": [1.3, 2.6, 5.0, 9.3, 16.6, 26.3]}
+
 # HBM bytes per batched fused-RK4 launch measured with rocprofv3 FETCH_SIZE /
 # WRITE_SIZE (scaled by the plain-copy calibration), for the kernel variant
 # and workload they were taken on (the hbm_counters summaries).  Reported
@@ -209,6 +216,9 @@ def main():
     traffic = MEASURED_TRAFFIC.get((fine_variant, args.config))
 
     extra = {}
+    if not args.no_per_config:
+        extra["per_config_fine_kernel"] = per_config_rates(pr, W, torch, kernel_of)
+        log("per-config F rates", extra["per_config_fine_kernel"])
     if not args.no_compare:
         # time-to-solution comparisons (outside the timed region)
         def timed(fn, reps=10, warm=3):
@@ -245,6 +255,14 @@ def main():
         t_serial = timed(lambda: pr.fine_sweep(p, u64, 0, p.nt_fine, u_out=out64), reps=5, warm=1)
         t_coarse = timed(lambda: pr.coarse_sweep(p, u64, 0, p.nt_coarse, u_out=out64), reps=5, warm=1)
         tau = (t_coarse / p.nt_coarse) / (t_serial / p.nt_fine)
+        # the same ratio for the paper's own setup (fourth-order F, 128^3)
+        pp = W.paper_setup(100.0)
+        upp = torch.from_numpy(W.synth_u0(pp.n, W.single_mode((1, 1, 1)))).cuda()
+        opp = torch.empty_like(upp)
+        t_fp = timed(lambda: pr.fine_sweep(pp, upp, 0, 256, u_out=opp), reps=5, warm=1) / 256
+        t_cp = timed(lambda: pr.coarse_sweep(pp, upp, 0, 64, u_out=opp), reps=5, warm=1) / 64
+        tau_paper = t_cp / t_fp
+        del upp, opp
         extra = {
             "time_to_solution_ms": {"parareal_batched": round(t_batched, 3),
                                     "parareal_batched_graph_replay": round(t_graph, 3),
@@ -255,6 +273,15 @@ def main():
             "batched_vs_plain_fp64_speedup": round(t_plain / t_batched, 3),
             "tau_c_over_tau_f_fp64_serial": round(tau, 4),
             "S_bound_eq_speedup": round(costmodel.speedup_bound(p.P, p.K, p.nc / p.nf, tau), 3),
+            # eq. speedup at the paper's K = 3 and N_f/N_c = 16 with this GPU's
+            # measured coarse/fine step-cost ratio, beside the paper's Table 1
+            "paper_table1_context": {
+                "hardware": "Piz Daint (Cray XC30): CPU = 8-core Xeon E5-2670 per node, GPU = one NVIDIA K20X "
+                            "per node; one time slice per node, K = 3, N_f/N_c = 16, 128^3",
+                **PAPER_TABLE1,
+                "tau_c_over_tau_f_paper_setup_this_gpu": round(tau_paper, 4),
+                "S_bound_with_this_gpu_tau": [round(costmodel.speedup_bound(n, 3, 1.0 / 16.0, tau_paper), 2)
+                                              for n in PAPER_TABLE1["nodes"]]},
         }
         # G on the grid coarsened by 2 (restriction, Euler steps with h = 2/n,
         # linear or cubic interpolation), with the smallest power-of-two coarse
@@ -322,10 +349,6 @@ def main():
             del um, u_fine64, uT_mixed, uT_plain
             torch.cuda.empty_cache()
             log("mixed comparison", extra["mixed_vs_plain_fp64"])
-
-    if not args.no_per_config:
-        extra["per_config_fine_kernel"] = per_config_rates(pr, W, torch, kernel_of)
-        log("per-config F rates", extra["per_config_fine_kernel"])
 
     cpu = None
     if not args.no_cpu_baseline:
