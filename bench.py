@@ -263,7 +263,7 @@ def main():
         t_cp = timed(lambda: pr.coarse_sweep(pp, upp, 0, 64, u_out=opp), reps=5, warm=1) / 64
         tau_paper = t_cp / t_fp
         del upp, opp
-        extra = {
+        extra.update({
             "time_to_solution_ms": {"parareal_batched": round(t_batched, 3),
                                     "parareal_batched_graph_replay": round(t_graph, 3),
                                     "first_call_with_graph_capture": round(t_capture, 3),
@@ -282,7 +282,7 @@ def main():
                 "tau_c_over_tau_f_paper_setup_this_gpu": round(tau_paper, 4),
                 "S_bound_with_this_gpu_tau": [round(costmodel.speedup_bound(n, 3, 1.0 / 16.0, tau_paper), 2)
                                               for n in PAPER_TABLE1["nodes"]]},
-        }
+        })
         # G on the grid coarsened by 2 (restriction, Euler steps with h = 2/n,
         # linear or cubic interpolation), with the smallest power-of-two coarse
         # count that the coarsened grid keeps stable
