@@ -96,7 +96,7 @@ def per_config_rates(pr, W, torch, kernel_of):
         es = 4 if mixed else 8
         u = torch.randn((p.P,) + tuple(reversed(p.n)), dtype=tdt, device="cuda")
         o = torch.empty_like(u)
-        steps = 16 if p.npts * p.P < (1 << 30) else 4
+        steps = 128 if p.npts * p.P < (1 << 27) else (16 if p.npts * p.P < (1 << 30) else 4)
         ms = ev_time(lambda k: pr.fine_sweep(p, u, [s * p.nf for s in range(p.P)], k, u_out=o), steps)
         lups = p.P * p.npts
         fv = pr.sweep_kernel_variant(p, pr.PR_FP32 if mixed else pr.PR_FP64, p.P, 0)
