@@ -118,7 +118,8 @@ def per_config_rates(pr, W, torch, kernel_of):
                             "gbs": round(lups * 8 / tm["fine_ms"] / 1e6, 1),
                             "frac": round(lups * 8 / tm["fine_ms"] / 1e6 / HBM_PEAK_GBS, 4),
                             "fine_launches": int(tm["fine_launches"]),
-                            "kernel": "%s (%s)" % (kernel_of(plan.kernel_variants()[0]), plan.kernel_variants()[0])}
+                            "kernel": "%s (%s)" % (kernel_of(plan.kernel_variants()[0]), plan.kernel_variants()[0]),
+                            "launch_groups": [{"variant": v, "instances": n} for v, _, n in plan.fine_groups()]}
     del plan, u0s
     torch.cuda.empty_cache()
     return out

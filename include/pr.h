@@ -198,7 +198,11 @@ size_t pr_defect_workspace_bytes(int32_t batch);
  *   ws      device workspace of pr_plan_workspace_bytes(probs, ninst, mode)
  *           bytes; owned by the caller, must outlive the plan
  * pr_plan_create validates everything (including stability unless
- * PR_ALLOW_UNSTABLE) and performs no kernel launch.
+ * PR_ALLOW_UNSTABLE) and performs no kernel launch.  Each instance takes the
+ * F variant chosen for its own grid (tuned, else built-in, at the batch of
+ * all slices of the instances with that grid); instances with the same
+ * choice form a launch group, and every fine step is one launch per group.
+ * G uses one variant for all instances.
  */
 size_t pr_plan_workspace_bytes(const pr_problem *probs, int32_t ninst, int32_t mode);
 int pr_plan_create(const pr_problem *probs, int32_t ninst, int32_t mode, void *ws, size_t ws_bytes,
@@ -225,8 +229,16 @@ int pr_parareal_solve(pr_plan *plan, const double *const *u0, double *const *uT,
 int pr_plan_iterations(const pr_plan *plan);
 
 /* Kernel variants the plan launches for F and G (HOST outputs, may be NULL);
- * names via pr_kernel_variant_name. */
+ * for F, the variant of the group with the most fine grid-point updates.
+ * Names via pr_kernel_variant_name. */
 int pr_plan_kernel_variants(const pr_plan *plan, int32_t *fine_variant, int32_t *coarse_variant);
+
+/* The plan's F launch groups: *count (HOST) receives the number of groups;
+ * the first min(count, max) entries of variant, blocks_per_cu (0: default
+ * layout) and instances (instances in the group) are filled, in the order
+ * of the groups' first instance.  The arrays may be NULL when max is 0. */
+int pr_plan_fine_groups(const pr_plan *plan, int32_t max, int32_t *count, int32_t *variant,
+                        int32_t *blocks_per_cu, int32_t *instances);
 
 /*
  * pr_plan_timings -- phase times of the last solve of a PR_MODE_TIMED plan
@@ -280,14 +292,16 @@ int pr_autotune(const pr_problem *prob, int32_t dtype, int32_t batch, int32_t wh
                 size_t ws_bytes, void *stream, int32_t *best_variant);
 
 /*
- * pr_plan_autotune -- tune the plan's own launches: every fused variant of F
- * that applies to all instances, with z chunks sized for 1, 2 and 4 blocks
- * per compute unit, timed on the batched F launch over all slices of all
- * instances; likewise G on the coarse chain's launch.  The plan keeps the
- * fastest (a recorded graph is re-recorded at the next solve).  Overwrites
- * the slice states in the workspace (the next solve starts from u0 anyway);
- * blocking.  Outputs (HOST, may be NULL): the chosen variants and blocks per
- * compute unit.  Results of later solves are bitwise the same as before.
+ * pr_plan_autotune -- tune the plan's own launches: for each F launch group,
+ * every fused variant of F that applies to all its instances, with z chunks
+ * sized for 1, 2 and 4 blocks per compute unit, timed on the group's F
+ * launch over all its slices; likewise G (one variant for all instances) on
+ * the coarse chain's launch.  The plan keeps the fastest (a recorded graph
+ * is re-recorded at the next solve).  Overwrites the slice states in the
+ * workspace (the next solve starts from u0 anyway); blocking.  Outputs
+ * (HOST, may be NULL): the choice of the group with the most fine work and
+ * of G, variant and blocks per compute unit.  Results of later solves are
+ * bitwise the same as before.
  */
 int pr_plan_autotune(pr_plan *plan, void *stream, int32_t *fine_variant, int32_t *fine_blocks_per_cu,
                      int32_t *coarse_variant, int32_t *coarse_blocks_per_cu);

@@ -241,6 +241,15 @@ class Plan:
         check(lib().pr_plan_kernel_variants(self._h, ctypes.byref(f), ctypes.byref(c)))
         return (lib().pr_kernel_variant_name(0, f.value).decode(), lib().pr_kernel_variant_name(1, c.value).decode())
 
+    def fine_groups(self):
+        """F launch groups: list of (variant name, blocks per CU, instances)."""
+        cnt = ctypes.c_int32()
+        check(lib().pr_plan_fine_groups(self._h, 0, ctypes.byref(cnt), None, None, None))
+        n = cnt.value
+        v, b, i = (ctypes.c_int32 * n)(), (ctypes.c_int32 * n)(), (ctypes.c_int32 * n)()
+        check(lib().pr_plan_fine_groups(self._h, n, ctypes.byref(cnt), v, b, i))
+        return [(lib().pr_kernel_variant_name(0, v[g]).decode(), b[g], i[g]) for g in range(n)]
+
     def timings(self):
         out = (ctypes.c_double * 6)()
         check(lib().pr_plan_timings(self._h, out))

@@ -21,7 +21,7 @@ STATUS_NAMES = {0: "PR_OK", -1: "PR_EINVAL", -2: "PR_EUNSTABLE", -3: "PR_ENOMEM"
 EXPORTS = ["pr_last_error", "pr_version", "pr_check_stability", "pr_fine_sweep", "pr_coarse_sweep",
            "pr_sweep_workspace_bytes", "pr_parareal_update", "pr_defect_norm", "pr_defect_workspace_bytes",
            "pr_plan_workspace_bytes", "pr_plan_create", "pr_plan_destroy", "pr_parareal_solve",
-           "pr_plan_iterations", "pr_plan_kernel_variants", "pr_plan_timings", "pr_plan_slice_state", "pr_set_kernel_variant",
+           "pr_plan_iterations", "pr_plan_kernel_variants", "pr_plan_fine_groups", "pr_plan_timings", "pr_plan_slice_state", "pr_set_kernel_variant",
            "pr_kernel_variant_count", "pr_kernel_variant_name", "pr_kernel_variant_info",
            "pr_autotune_workspace_bytes", "pr_autotune", "pr_plan_autotune", "pr_transfer_workspace_bytes",
            "pr_restrict", "pr_prolong", "pr_sweep_kernel_variant"]
@@ -79,6 +79,7 @@ def lib():
     L.pr_parareal_solve.argtypes = [_vp, ctypes.POINTER(_vp), ctypes.POINTER(_vp), ctypes.POINTER(_vp), _dp, _vp]
     L.pr_plan_iterations.argtypes = [_vp]
     L.pr_plan_kernel_variants.argtypes = [_vp, ctypes.POINTER(_i32), ctypes.POINTER(_i32)]
+    L.pr_plan_fine_groups.argtypes = [_vp, _i32] + [ctypes.POINTER(_i32)] * 4
     L.pr_plan_timings.argtypes = [_vp, _dp]
     L.pr_plan_slice_state.argtypes = [_vp, _i32, _i32, ctypes.POINTER(_vp)]
     L.pr_set_kernel_variant.argtypes = [_i32, _i32]

@@ -490,8 +490,8 @@ struct pr_plan {
     int dtype = PR_FP64;  // sweep dtype
     int K = 0;
     uint32_t flags = 0;
-    int fine_v = 0, coarse_v = 0;
-    int fine_bpc = 0, coarse_bpc = 0;   // blocks-per-CU targets of the layouts (0: default)
+    int coarse_v = 0;
+    int coarse_bpc = 0;   // blocks-per-CU target of the coarse layout (0: default)
     bool mixed = false, per_slice = false, graph = false, timed = false, skip = false, early = false;
     std::vector<pr_problem> probs;
     int Pmax = 0;
@@ -508,13 +508,23 @@ struct pr_plan {
     };
     std::vector<Inst> inst;
 
+    // F launch groups: instances that share a fused variant and layout.  Each
+    // group is one launch per fine step; groups hold disjoint instances.
+    struct FineGroup {
+        int v = 0, bpc = 0;                      // variant, blocks-per-CU target (0: default)
+        std::vector<int> insts;                  // instance indices
+        std::vector<int> off, cnt;               // per k: offset into fine_tab, items
+        std::vector<std::vector<int>> active;    // per k, per step j: blocks of the active prefix
+    };
+    std::vector<FineGroup> fgroups;
+    std::vector<int> inst_group;        // instance -> group
+
     // device tables
-    ItemDesc *fine_tab = nullptr;       // K tables of nfine[k] items (batched layout)
-    std::vector<int> fine_off, fine_cnt;   // per k: offset into fine_tab, items
-    std::vector<std::vector<int>> fine_active_blocks;  // per k, per step j: blocks of active prefix
+    ItemDesc *fine_tab = nullptr;       // per k and group: the group's items (batched layout)
     ItemDesc *slice_tab = nullptr;      // per-slice layout: all (i, n), block_begin = 0
     std::vector<int> slice_index;       // (i, n) -> index into slice_tab
     std::vector<int> slice_blocks;      // blocks of each slice_tab item
+    std::vector<int> slice_var;         // fine variant of each slice_tab item
     ItemDesc *coarse_tab = nullptr;     // [parity][n] -> up to ninst items
     bool coarsen = false;               // PR_COARSEN_G: G = prolong(coarse sweep(restrict(U)))
     int iorder = 1;                     // interpolation order of the coarsened G
@@ -664,16 +674,32 @@ int upload(T *dev, const std::vector<T> &host)
 
 char *slice_ptr(char *base, int n, int64_t npts, size_t es) { return base + (size_t)n * npts * es; }
 
+// The F group with the most fine LUPs per solve (the plan's dominant launch).
+int primary_group(const pr_plan *pl)
+{
+    int best = 0;
+    double most = -1;
+    for (int g = 0; g < (int)pl->fgroups.size(); ++g) {
+        double w = 0;
+        for (int i : pl->fgroups[g].insts) w += (double)pl->inst[i].npts * pl->inst[i].P * pl->inst[i].nf;
+        if (w > most) {
+            most = w;
+            best = g;
+        }
+    }
+    return best;
+}
+
 int build_tables(pr_plan *pl)
 {
     const size_t es = esize(pl->dtype);
     const int ninst = pl->ninst;
     const int K = pl->K;
-    const VariantInfo *fvi = fine_info(pl->fine_v);
     const VariantInfo *cvi = coarse_info(pl->coarse_v);
-    const bool fref = pl->fine_v == 1, cref = pl->coarse_v == 1;
-    for (const auto &in : pl->inst)
-        if (fref && !in.Fscr) return fail(PR_EINVAL, "kernel variant changed between workspace query and plan creation");
+    const bool cref = pl->coarse_v == 1;
+    for (int i = 0; i < ninst; ++i)
+        if (pl->fgroups[pl->inst_group[i]].v == 1 && !pl->inst[i].Fscr)
+            return fail(PR_EINVAL, "kernel variant changed between workspace query and plan creation");
 
     pl->slice_base.resize(ninst);
     for (int i = 0, b = 0; i < ninst; ++i) {
@@ -694,32 +720,36 @@ int build_tables(pr_plan *pl)
         return it;
     };
 
-    // batched fine tables, one per iteration (slices n >= k when skipping)
+    // batched fine tables, one per iteration and group (slices n >= k when
+    // skipping); items sorted by step count so that the active blocks of
+    // step j are a prefix of the grid
     std::vector<ItemDesc> all;
-    pl->fine_off.assign(std::max(K, 1), 0);
-    pl->fine_cnt.assign(std::max(K, 1), 0);
-    pl->fine_active_blocks.assign(std::max(K, 1), {});
-    for (int k = 0; k < K; ++k) {
-        std::vector<ItemDesc> items;
-        for (int i = 0; i < ninst; ++i)
-            for (int n = (pl->skip ? k : 0); n < pl->inst[i].P; ++n) items.push_back(fine_item(i, n));
-        std::stable_sort(items.begin(), items.end(),
-                         [](const ItemDesc &a, const ItemDesc &b) { return a.nsteps > b.nsteps; });
-        const int nb = layout(items, fvi, fref, 8, pl->fine_bpc);
-        (void)nb;
-        int maxsteps = items.empty() ? 0 : items[0].nsteps;
-        std::vector<int> act(maxsteps, 0);
-        for (int j = 0; j < maxsteps; ++j) {
-            int blocks = 0;
-            for (auto &it : items)
-                if (it.nsteps > j) blocks = it.block_begin + it.nblocks;
-            act[j] = blocks;
-        }
-        pl->fine_active_blocks[k] = act;
-        pl->fine_off[k] = (int)all.size();
-        pl->fine_cnt[k] = (int)items.size();
-        all.insert(all.end(), items.begin(), items.end());
+    for (auto &g : pl->fgroups) {
+        g.off.assign(std::max(K, 1), 0);
+        g.cnt.assign(std::max(K, 1), 0);
+        g.active.assign(std::max(K, 1), {});
     }
+    for (int k = 0; k < K; ++k)
+        for (auto &g : pl->fgroups) {
+            std::vector<ItemDesc> items;
+            for (int i : g.insts)
+                for (int n = (pl->skip ? k : 0); n < pl->inst[i].P; ++n) items.push_back(fine_item(i, n));
+            std::stable_sort(items.begin(), items.end(),
+                             [](const ItemDesc &a, const ItemDesc &b) { return a.nsteps > b.nsteps; });
+            layout(items, fine_info(g.v), g.v == 1, 8, g.bpc);
+            const int maxsteps = items.empty() ? 0 : items[0].nsteps;
+            std::vector<int> act(maxsteps, 0);
+            for (int j = 0; j < maxsteps; ++j) {
+                int blocks = 0;
+                for (auto &it : items)
+                    if (it.nsteps > j) blocks = it.block_begin + it.nblocks;
+                act[j] = blocks;
+            }
+            g.active[k] = act;
+            g.off[k] = (int)all.size();
+            g.cnt[k] = (int)items.size();
+            all.insert(all.end(), items.begin(), items.end());
+        }
     int rc = upload(pl->fine_tab, all);
     if (rc) return rc;
 
@@ -727,12 +757,15 @@ int build_tables(pr_plan *pl)
     std::vector<ItemDesc> sl;
     pl->slice_index.assign(pl->sumP, 0);
     pl->slice_blocks.clear();
+    pl->slice_var.clear();
     for (int i = 0; i < ninst; ++i)
         for (int n = 0; n < pl->inst[i].P; ++n) {
+            const int v = pl->fgroups[pl->inst_group[i]].v;
             std::vector<ItemDesc> one{fine_item(i, n)};
-            layout(one, fvi, fref, 8);
+            layout(one, fine_info(v), v == 1, 8);
             pl->slice_index[pl->slice_base[i] + n] = (int)sl.size();
             pl->slice_blocks.push_back(one[0].nblocks);
+            pl->slice_var.push_back(v);
             sl.push_back(one[0]);
         }
     rc = upload(pl->slice_tab, sl);
@@ -867,11 +900,12 @@ int enqueue_init(pr_plan *pl, hipStream_t s)
 int enqueue_fine(pr_plan *pl, int k, hipStream_t s)
 {
     if (!pl->per_slice) {
-        const ItemDesc *tab = pl->fine_tab + pl->fine_off[k];
-        const int cnt = pl->fine_cnt[k];
-        const std::vector<int> &act = pl->fine_active_blocks[k];
-        for (int j = 0; j < (int)act.size(); ++j)
-            HIPCHK(pr::launch_fine_step(pl->fine_v, pl->dtype, pl->probs[0].fine_order, tab, cnt, act[j], j, s));
+        for (const auto &g : pl->fgroups) {
+            const ItemDesc *tab = pl->fine_tab + g.off[k];
+            const std::vector<int> &act = g.active[k];
+            for (int j = 0; j < (int)act.size(); ++j)
+                HIPCHK(pr::launch_fine_step(g.v, pl->dtype, pl->probs[0].fine_order, tab, g.cnt[k], act[j], j, s));
+        }
     } else {
         for (int i = 0; i < pl->ninst; ++i)
             for (int n = (pl->skip ? k : 0); n < pl->inst[i].P; ++n) {
@@ -879,7 +913,7 @@ int enqueue_fine(pr_plan *pl, int k, hipStream_t s)
                 const ItemDesc *tab = pl->slice_tab + idx;
                 const int nf = pl->inst[i].nf;
                 for (int j = 0; j < nf; ++j)
-                    HIPCHK(pr::launch_fine_step(pl->fine_v, pl->dtype, pl->probs[i].fine_order, tab, 1,
+                    HIPCHK(pr::launch_fine_step(pl->slice_var[idx], pl->dtype, pl->probs[i].fine_order, tab, 1,
                                                 pl->slice_blocks[idx], j, s));
             }
     }
@@ -961,7 +995,7 @@ int count_launches(const pr_plan *pl, double *nf, double *ng)
     double f = 0, g = 0;
     for (int k = 0; k < pl->iters_done; ++k) {
         if (!pl->per_slice) {
-            f += (double)pl->fine_active_blocks[k].size();
+            for (const auto &gr : pl->fgroups) f += (double)gr.active[k].size();
         } else {
             for (int i = 0; i < pl->ninst; ++i)
                 for (int n = (pl->skip ? k : 0); n < pl->inst[i].P; ++n) f += pl->inst[i].nf;
@@ -1162,41 +1196,63 @@ int pr_plan_create(const pr_problem *probs, int32_t ninst, int32_t mode, void *w
     pl->coarsen = (pl->flags & PR_COARSEN_G) != 0;
     pl->iorder = interp_order(probs[0]);
 
-    // one fused variant for all instances: the choice for instance 0 if it
-    // applies to every instance, else the generic one-point-per-thread layout
-    int sumP0 = 0;
-    for (int i = 0; i < ninst; ++i) sumP0 += probs[i].P;
-    const Choice fch = pick_fine(probs[0], pl->dtype, sumP0), cch = pick_coarse(coarse_grid(probs[0]), pl->dtype, ninst);
-    int fv = fch.v, cv = cch.v;
-    bool fok = fv >= 1, cok = cv >= 1;
-    for (int i = 0; i < ninst; ++i) {
-        fok = fok && fine_applicable(fv, pl->dtype, probs[i].fine_order, probs[i]);
-        cok = cok && coarse_applicable(cv, pl->dtype, coarse_grid(probs[i]));
+    for (int i = 0; i < ninst; ++i)
         if (probs[i].fine_order != probs[0].fine_order) {
             delete pl;
             return fail(PR_EUNSUPPORTED, "instances of one plan must share fine_order");
         }
-    }
-    // fallback: the tiled default for a generic n_x, even if every instance
-    // has an even n_x (two x points per thread), else odd (one per thread)
-    bool all_even = true, all_even_c = true;
+    // F: every instance takes the choice for its own grid, at the batch of
+    // all slices of the instances with that grid; instances with the same
+    // choice share one launch per step (a group).  A forced variant must
+    // apply to every instance and gives a single group.
+    pl->inst_group.assign(ninst, 0);
     for (int i = 0; i < ninst; ++i) {
-        all_even = all_even && probs[i].n[0] % 2 == 0;
+        Choice c;
+        if (g_fine_forced) {
+            c = Choice{g_fine_forced, g_bpc_forced};
+            if (!fine_applicable(c.v, pl->dtype, probs[i].fine_order, probs[i])) {
+                delete pl;
+                return fail(PR_EUNSUPPORTED, "forced kernel variant does not apply to every instance");
+            }
+        } else {
+            int batch = 0;
+            for (int j = 0; j < ninst; ++j)
+                if (probs[j].n[0] == probs[i].n[0] && probs[j].n[1] == probs[i].n[1] && probs[j].n[2] == probs[i].n[2])
+                    batch += probs[j].P;
+            c = pick_fine(probs[i], pl->dtype, batch);
+            if (c.v < 1 || !fine_applicable(c.v, pl->dtype, probs[i].fine_order, probs[i]))
+                c = Choice{pick_fine_default(probs[i], pl->dtype, batch), 0};
+        }
+        int g = 0;
+        while (g < (int)pl->fgroups.size() && !(pl->fgroups[g].v == c.v && pl->fgroups[g].bpc == c.bpc)) ++g;
+        if (g == (int)pl->fgroups.size()) {
+            pl->fgroups.emplace_back();
+            pl->fgroups.back().v = c.v;
+            pl->fgroups.back().bpc = c.bpc;
+        }
+        pl->fgroups[g].insts.push_back(i);
+        pl->inst_group[i] = g;
+    }
+    // G: one fused variant for all instances (the chain's launches are per
+    // slice boundary): the choice for instance 0 if it applies to every
+    // instance, else the tiled default for a generic n_x, even if every
+    // instance has an even n_x (two x points per thread), else odd
+    const Choice cch = pick_coarse(coarse_grid(probs[0]), pl->dtype, ninst);
+    int cv = cch.v;
+    bool cok = cv >= 1;
+    bool all_even_c = true;
+    for (int i = 0; i < ninst; ++i) {
+        cok = cok && coarse_applicable(cv, pl->dtype, coarse_grid(probs[i]));
         all_even_c = all_even_c && coarse_grid(probs[i]).n[0] % 2 == 0;
     }
-    pr_problem generic = probs[0];
-    generic.n[0] = all_even ? 2 : 3;
     pr_problem generic_c = coarse_grid(probs[0]);
     generic_c.n[0] = all_even_c ? 2 : 3;
-    if (!fok) fv = g_fine_forced ? -1 : pick_fine_default(generic, pl->dtype, sumP0);
     if (!cok) cv = g_coarse_forced ? -1 : pick_coarse_default(generic_c, pl->dtype);
-    if (fv < 1 || cv < 1) {
+    if (cv < 1) {
         delete pl;
         return fail(PR_EUNSUPPORTED, "forced kernel variant does not apply to every instance");
     }
-    pl->fine_v = fv;
     pl->coarse_v = cv;
-    pl->fine_bpc = fok ? fch.bpc : 0;
     pl->coarse_bpc = cok ? cch.bpc : 0;
 
     plan_layout(probs, ninst, mode, (char *)ws, pl);
@@ -1235,8 +1291,24 @@ int pr_plan_iterations(const pr_plan *plan) { return plan ? plan->iters_done : 0
 int pr_plan_kernel_variants(const pr_plan *plan, int32_t *fine_variant, int32_t *coarse_variant)
 {
     if (!plan) return fail(PR_EINVAL, "plan is NULL");
-    if (fine_variant) *fine_variant = plan->fine_v;
+    if (fine_variant) *fine_variant = plan->fgroups[primary_group(plan)].v;
     if (coarse_variant) *coarse_variant = plan->coarse_v;
+    return PR_OK;
+}
+
+int pr_plan_fine_groups(const pr_plan *plan, int32_t max, int32_t *count, int32_t *variant,
+                        int32_t *blocks_per_cu, int32_t *instances)
+{
+    if (!plan || !count) return fail(PR_EINVAL, "NULL argument");
+    if (max < 0) return fail(PR_EINVAL, "max must be >= 0");
+    if (max > 0 && (!variant || !blocks_per_cu || !instances)) return fail(PR_EINVAL, "NULL output array");
+    const int ng = (int)plan->fgroups.size();
+    *count = ng;
+    for (int g = 0; g < ng && g < max; ++g) {
+        variant[g] = plan->fgroups[g].v;
+        blocks_per_cu[g] = plan->fgroups[g].bpc;
+        instances[g] = (int32_t)plan->fgroups[g].insts.size();
+    }
     return PR_OK;
 }
 
@@ -1557,19 +1629,25 @@ int pr_plan_autotune(pr_plan *pl, void *stream, int32_t *fine_variant, int32_t *
     HIPCHK(hipEventCreate(&e0));
     HIPCHK(hipEventCreate(&e1));
     static const int kBpc[] = {1, 2, 4};
-    const int saved[4] = {pl->fine_v, pl->fine_bpc, pl->coarse_v, pl->coarse_bpc};
-    auto applies = [&](int which, int v) {
-        for (const auto &p : pl->probs) {
+    std::vector<Choice> saved_f;
+    for (const auto &g : pl->fgroups) saved_f.push_back(Choice{g.v, g.bpc});
+    const Choice saved_g{pl->coarse_v, pl->coarse_bpc};
+    // F candidates must apply to every instance of the group, G candidates
+    // to every instance
+    auto applies = [&](int which, int grp, int v) {
+        for (int i = 0; i < pl->ninst; ++i) {
+            const pr_problem &p = pl->probs[i];
+            if (which == 0 && pl->inst_group[i] != grp) continue;
             const bool ok = which == 0 ? fine_applicable(v, pl->dtype, p.fine_order, p)
                                        : coarse_applicable(v, pl->dtype, coarse_grid(p));
             if (!ok) return false;
         }
         return true;
     };
-    // time F step launches over all slices (iteration 0 table), and coarse
-    // chunks of the chain (slice 0 table) covering at least 12 Euler steps;
-    // the figure compared is the time per step
-    auto time_one = [&](int which, float *ms_out) -> int {
+    // time F step launches of one group over all its slices (iteration 0
+    // table), and coarse chunks of the chain (slice 0 table) covering at
+    // least 12 Euler steps; the figure compared is the time per step
+    auto time_one = [&](int which, int grp, float *ms_out) -> int {
         int r = build_tables(pl);
         if (r) return r;
         const int S = which == 0 ? 1 : coarse_steps_per_launch(pl->coarse_v);
@@ -1578,10 +1656,10 @@ int pr_plan_autotune(pr_plan *pl, void *stream, int32_t *fine_variant, int32_t *
             if (rep == 1) HIPCHK(hipEventRecord(e0, s));
             for (int t = 0; t < launches; ++t) {
                 if (which == 0) {
-                    if (pl->fine_active_blocks.empty() || pl->fine_active_blocks[0].empty()) break;
-                    HIPCHK(pr::launch_fine_step(pl->fine_v, pl->dtype, pl->probs[0].fine_order,
-                                                pl->fine_tab + pl->fine_off[0], pl->fine_cnt[0],
-                                                pl->fine_active_blocks[0][0], 0, s));
+                    const auto &g = pl->fgroups[grp];
+                    if (g.active.empty() || g.active[0].empty()) break;
+                    HIPCHK(pr::launch_fine_step(g.v, pl->dtype, pl->probs[0].fine_order, pl->fine_tab + g.off[0],
+                                                g.cnt[0], g.active[0][0], 0, s));
                 } else {
                     if (pl->coarse_cnt.empty() || !pl->coarse_cnt[0]) break;
                     HIPCHK(pr::launch_coarse_chunk(pl->coarse_v, pl->dtype, pl->coarse_tab, pl->coarse_cnt[0],
@@ -1596,47 +1674,53 @@ int pr_plan_autotune(pr_plan *pl, void *stream, int32_t *fine_variant, int32_t *
         *ms_out = ms / (float)(launches * S);
         return PR_OK;
     };
-    Choice bestf{saved[0], saved[1]}, bestg{saved[2], saved[3]};
-    for (int which = 0; which < 2 && rc == PR_OK; ++which) {
+    // one pass per F group, then G
+    const int ngrp = (int)pl->fgroups.size();
+    for (int pass = 0; pass <= ngrp && rc == PR_OK; ++pass) {
+        const int which = pass < ngrp ? 0 : 1;
+        const int grp = pass < ngrp ? pass : -1;
         if (which == 0 && pl->K == 0) continue;   // no fine sweep in the solve
+        Choice best_c = which == 0 ? saved_f[grp] : saved_g;
         float best = 1e30f;
         const int nv = which == 0 ? pr::fine_variant_count() : pr::coarse_variant_count();
         for (int v = 2; v < nv && rc == PR_OK; ++v) {
-            if (!applies(which, v)) continue;
+            if (!applies(which, grp, v)) continue;
             const VariantInfo *vi = which == 0 ? pr::fine_variant(v) : pr::coarse_variant(v);
             if (which == 0 && vi->order != pl->probs[0].fine_order) continue;
             for (int bpc : kBpc) {
                 if (which == 0) {
-                    pl->fine_v = v;
-                    pl->fine_bpc = bpc;
+                    pl->fgroups[grp].v = v;
+                    pl->fgroups[grp].bpc = bpc;
                 } else {
                     pl->coarse_v = v;
                     pl->coarse_bpc = bpc;
                 }
                 float ms = 0;
-                rc = time_one(which, &ms);
+                rc = time_one(which, grp, &ms);
                 if (rc) break;
                 if (ms < best) {
                     best = ms;
-                    (which == 0 ? bestf : bestg) = Choice{v, bpc};
+                    best_c = Choice{v, bpc};
                 }
             }
         }
         if (which == 0) {
-            pl->fine_v = bestf.v;
-            pl->fine_bpc = bestf.bpc;
+            pl->fgroups[grp].v = best_c.v;
+            pl->fgroups[grp].bpc = best_c.bpc;
         } else {
-            pl->coarse_v = bestg.v;
-            pl->coarse_bpc = bestg.bpc;
+            pl->coarse_v = best_c.v;
+            pl->coarse_bpc = best_c.bpc;
         }
     }
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
     if (rc) {
-        pl->fine_v = saved[0];
-        pl->fine_bpc = saved[1];
-        pl->coarse_v = saved[2];
-        pl->coarse_bpc = saved[3];
+        for (int g = 0; g < ngrp; ++g) {
+            pl->fgroups[g].v = saved_f[g].v;
+            pl->fgroups[g].bpc = saved_f[g].bpc;
+        }
+        pl->coarse_v = saved_g.v;
+        pl->coarse_bpc = saved_g.bpc;
     }
     int r2 = build_tables(pl);
     if (!rc) rc = r2;
@@ -1650,8 +1734,9 @@ int pr_plan_autotune(pr_plan *pl, void *stream, int32_t *fine_variant, int32_t *
         pl->graph_h = nullptr;
     }
     if (rc) return rc;
-    if (fine_variant) *fine_variant = pl->fine_v;
-    if (fine_blocks_per_cu) *fine_blocks_per_cu = pl->fine_bpc;
+    const int pg = primary_group(pl);
+    if (fine_variant) *fine_variant = pl->fgroups[pg].v;
+    if (fine_blocks_per_cu) *fine_blocks_per_cu = pl->fgroups[pg].bpc;
     if (coarse_variant) *coarse_variant = pl->coarse_v;
     if (coarse_blocks_per_cu) *coarse_blocks_per_cu = pl->coarse_bpc;
     return PR_OK;

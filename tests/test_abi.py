@@ -260,5 +260,7 @@ def test_grid_transfer_validation_without_device():
 
 def test_plan_autotune_validation():
     L = _lib()
+    cnt = ctypes.c_int32()
+    assert L.lib().pr_plan_fine_groups(None, 0, ctypes.byref(cnt), None, None, None) == L.PR_EINVAL
     v = (ctypes.c_int32 * 4)()
     assert L.lib().pr_plan_autotune(None, None, None, None, None, None) == L.PR_EINVAL

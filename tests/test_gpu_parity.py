@@ -432,6 +432,39 @@ def test_multi_instance_whole_row_kernels(pr, orc):
         assert np.array_equal(one[0], got), i
 
 
+def test_multi_instance_launch_groups(pr, orc):
+    """Instances whose grids call for different F kernels (whole-row at
+    n_x = 128, tiled at n_x = 48) run as separate launch groups of one plan:
+    every instance matches the oracle, and the batched, per-slice and
+    graph-replayed solves, before and after tuning, agree bit for bit with
+    the single-instance solves."""
+    probs, u0s = [], []
+    for i, (n3, a, nu0, nf, nc) in enumerate([((128, 24, 16), (0.7, -0.4, 0.2), 0.002, 8, 8),
+                                              ((48, 36, 20), (-0.6, 0.5, 0.4), 0.004, 6, 4),
+                                              ((128, 40, 12), (-0.5, 0.9, 0.3), 0.001, 10, 10)]):
+        p = W.small_problem(n=n3, a=a, nu0=nu0, P=3, nf=nf, nc=nc, K=2)
+        probs.append(p)
+        u0s.append(W.random_field(p.n, 270 + i))
+    for mode in (pr.PR_MODE_FP64, pr.PR_MODE_MIXED):
+        say("launch groups mode", mode)
+        singles = [_solve(pr, [p], [u0s[i]], mode)[0][0] for i, p in enumerate(probs)]
+        if mode == pr.PR_MODE_FP64:
+            for i, p in enumerate(probs):
+                U, _ = orc.parareal(p, u0s[i], K=p.K)
+                assert rel_l2(singles[i], U[-1]) <= FP64_TOL, i
+        for extra in (0, pr.PR_MODE_PER_SLICE, pr.PR_MODE_GRAPH):
+            plan = pr.Plan(probs, mode | extra)
+            groups = plan.fine_groups()
+            assert len(groups) == 2 and sorted(g[2] for g in groups) == [1, 2], groups
+            assert any(g[0].startswith("rk4w_") for g in groups), groups
+            for rep in range(2):
+                if rep == 1:
+                    plan.autotune()
+                uT, _ = plan.solve([cuda(u) for u in u0s])
+                for i in range(len(probs)):
+                    assert np.array_equal(host(uT[i]), singles[i]), (mode, extra, rep, i)
+
+
 def test_reference_defect_and_early_stop(pr, orc):
     import torch
     p = W.small_problem(n=(24, 24, 24), P=4, nf=6, nc=5, K=4)
