@@ -384,6 +384,25 @@ int layout(std::vector<ItemDesc> &items, const VariantInfo *vi, bool ref, int zm
         bxy += (int64_t)it.tiles_x * it.tiles_y;
     }
     int want = (int)std::max<int64_t>(1, (target + bxy - 1) / std::max<int64_t>(bxy, 1));
+    // Enough tiles for every slot at one z chunk per tile: the launch runs in
+    // rounds of `target` blocks.  Take the chunk count (up to 4) with the
+    // fewest rounds x planes per block (chunk depth plus the 8-plane pipeline
+    // fill), so that a last, partly filled round of full-depth blocks is
+    // traded for shorter blocks when that is cheaper.
+    if (bxy >= target) {
+        int nzmax = 1;
+        for (const auto &it : items) nzmax = std::max(nzmax, it.nz);
+        int64_t best = INT64_MAX;
+        for (int zc = 1; zc <= 4; ++zc) {
+            if (zc > 1 && nzmax / zc < zmin) break;
+            const int64_t rounds = (bxy * zc + target - 1) / target;
+            const int64_t cost = rounds * ((nzmax + zc - 1) / zc + 8);
+            if (cost < best) {
+                best = cost;
+                want = zc;
+            }
+        }
+    }
     int b = 0;
     for (auto &it : items) {
         const int maxz = std::max(1, it.nz / zmin);
