@@ -280,8 +280,9 @@ int pr_sweep_kernel_variant(const pr_problem *prob, int32_t dtype, int32_t batch
 
 /*
  * pr_autotune -- time the fused variants of F (which = 0) or G (which = 1)
- * for this problem and batch on the device, each with z chunks sized for 1,
- * 2 and 4 blocks per compute unit, and remember the fastest pair for (grid,
+ * for this problem and batch on the device, each with z chunks sized for the
+ * kernel's resident blocks per compute unit (reported as 0) and for 1, 2
+ * and 4 blocks per compute unit, and remember the fastest pair for (grid,
  * dtype, fine_order, batch); sweeps of that shape then use it (the entry of
  * their batch, else any tuned batch of the shape).  Scratch buffers come
  * from `ws` (pr_autotune_workspace_bytes).  Blocking.  best_variant (HOST,
@@ -294,7 +295,8 @@ int pr_autotune(const pr_problem *prob, int32_t dtype, int32_t batch, int32_t wh
 /*
  * pr_plan_autotune -- tune the plan's own launches: for each F launch group,
  * every fused variant of F that applies to all its instances, with z chunks
- * sized for 1, 2 and 4 blocks per compute unit, timed on the group's F
+ * sized as in pr_autotune (0: resident blocks, or 1, 2, 4 blocks per compute
+ * unit), timed on the group's F
  * launch over all its slices; likewise G (one variant for all instances) on
  * the coarse chain's launch.  The plan keeps the fastest (a recorded graph
  * is re-recorded at the next solve).  Overwrites the slice states in the

@@ -282,11 +282,29 @@ int pick_fine_default(const pr_problem &p, int dtype, int batch)
                : p.n[0] == 128 ? "rk4w_f64_x128_y8_p2x1_w16"
                : p.n[0] == 64  ? "rk4w_f64_x64_y8_p1x1_w16"
                                : "rk4b_f64_t32x32_p1x2_d2";
-    else
+    else if (order == 2 && even && p.n[0] != 256 && p.n[0] != 128) {
+        // two x points per thread, tiled: the tile that computes the fewest
+        // points per output point of this grid in x and y (halo of 4 per side)
+        static const char *const kTiled[] = {"rk4b_f32_t64x32_p2x2_d2", "rk4b_f32_t64x24_p2x2_d2",
+                                             "rk4b_f32_t48x32_p2x2_d2", "rk4b_f32_t48x24_p2x2_d2"};
+        int best_v = -1;
+        double best = 1e300;
+        for (const char *nm : kTiled) {
+            const int v = find_fine(nm);
+            const VariantInfo *vi = pr::fine_variant(v);
+            if (!vi) continue;
+            const double wx = (double)((p.n[0] + vi->tx - 1) / vi->tx) * (vi->tx + 8) / p.n[0];
+            const double wy = (double)((p.n[1] + vi->ty - 1) / vi->ty) * (vi->ty + 8) / p.n[1];
+            if (wx * wy < best * (1 - 1e-12)) {
+                best = wx * wy;
+                best_v = v;
+            }
+        }
+        return best_v;
+    } else
         name = order == 4 ? (even ? "rk4_f32_o4_t32x16_p2x2" : "rk4_f32_o4_t32x16_p1x2")
                : p.n[0] == 256 ? "rk4w_f32_x256_y8_p4x2_w8"
                : p.n[0] == 128 ? (batch >= 4 ? "rk4w_f32_x128_y16_p2x3_w8" : "rk4w_f32_x128_y8_p2x1_w16")
-               : even          ? "rk4b_f32_t64x32_p2x2_d2"
                                : "rk4b_f32_t32x32_p1x4_d2";
     return find_fine(name);
 }
@@ -354,17 +372,15 @@ void fill_item(ItemDesc &it, const pr_problem &p, bool fine)
     it.frozen = (fine && (p.flags & PR_NU_FROZEN)) ? 1 : 0;
 }
 
-// Tile layout of a set of items for a variant; block ranges are assigned in
-// item order.  Returns the total number of blocks.
-int g_blocks_per_cu = 0;  // launch-size target of the tile layout (0: default)
-
-int layout(std::vector<ItemDesc> &items, const VariantInfo *vi, bool ref, int zmin, int bpc = 0)
+// Tile layout of a launch: tiles per item, z chunks and block ranges
+// (assigned in item order); returns the total number of blocks.  occ =
+// resident blocks per compute unit of the variant; bpc = blocks per compute
+// unit that the z chunking aims for (0: occ).
+int layout(std::vector<ItemDesc> &items, const VariantInfo *vi, bool ref, int zmin, int bpc, int occ)
 {
-    if (g_blocks_per_cu == 0) {
-        const char *e = getenv("PR_BLOCKS_PER_CU");
-        g_blocks_per_cu = e ? std::max(1, atoi(e)) : 1;
-    }
-    const int target = (bpc > 0 ? bpc : g_blocks_per_cu) * std::max(g_num_cus, 1);
+    const int cus = std::max(g_num_cus, 1);
+    const int64_t target = (int64_t)(bpc > 0 ? bpc : std::max(occ, 1)) * cus;
+    const int64_t cap = (int64_t)std::max(occ, 1) * cus;
     if (ref) {
         int b = 0;
         for (auto &it : items) {
@@ -384,18 +400,18 @@ int layout(std::vector<ItemDesc> &items, const VariantInfo *vi, bool ref, int zm
         bxy += (int64_t)it.tiles_x * it.tiles_y;
     }
     int want = (int)std::max<int64_t>(1, (target + bxy - 1) / std::max<int64_t>(bxy, 1));
-    // Enough tiles for every slot at one z chunk per tile: the launch runs in
-    // rounds of `target` blocks.  Take the chunk count (up to 4) with the
-    // fewest rounds x planes per block (chunk depth plus the 8-plane pipeline
-    // fill), so that a last, partly filled round of full-depth blocks is
-    // traded for shorter blocks when that is cheaper.
+    // Enough tiles for the target at one z chunk per tile: the launch runs in
+    // rounds of `cap` resident blocks.  Take the chunk count (up to 4) with
+    // the fewest rounds x planes per block (chunk depth plus the 8-plane
+    // pipeline fill), so that a last, partly filled round of full-depth
+    // blocks is traded for shorter blocks when that is cheaper.
     if (bxy >= target) {
         int nzmax = 1;
         for (const auto &it : items) nzmax = std::max(nzmax, it.nz);
         int64_t best = INT64_MAX;
         for (int zc = 1; zc <= 4; ++zc) {
             if (zc > 1 && nzmax / zc < zmin) break;
-            const int64_t rounds = (bxy * zc + target - 1) / target;
+            const int64_t rounds = (bxy * zc + cap - 1) / cap;
             const int64_t cost = rounds * ((nzmax + zc - 1) / zc + 8);
             if (cost < best) {
                 best = cost;
@@ -484,7 +500,8 @@ int sweep_common(const pr_problem *prob_in, int dtype, int batch, const void *u_
     }
     const VariantInfo *vi = fine ? fine_info(v) : coarse_info(v);
     const int zmin = fine ? 8 : 4;
-    const int nblocks = layout(items, vi, ref, zmin, ch.bpc);
+    const int occ = fine ? pr::fine_occupancy(v) : pr::coarse_occupancy(v);
+    const int nblocks = layout(items, vi, ref, zmin, ch.bpc, occ);
     HIPCHK(pr::launch_write_items(items.data(), batch, table, s));
     if (fine) {
         for (int j = 0; j < nsteps; ++j)
@@ -755,7 +772,7 @@ int build_tables(pr_plan *pl)
                 for (int n = (pl->skip ? k : 0); n < pl->inst[i].P; ++n) items.push_back(fine_item(i, n));
             std::stable_sort(items.begin(), items.end(),
                              [](const ItemDesc &a, const ItemDesc &b) { return a.nsteps > b.nsteps; });
-            layout(items, fine_info(g.v), g.v == 1, 8, g.bpc);
+            layout(items, fine_info(g.v), g.v == 1, 8, g.bpc, pr::fine_occupancy(g.v));
             const int maxsteps = items.empty() ? 0 : items[0].nsteps;
             std::vector<int> act(maxsteps, 0);
             for (int j = 0; j < maxsteps; ++j) {
@@ -781,7 +798,7 @@ int build_tables(pr_plan *pl)
         for (int n = 0; n < pl->inst[i].P; ++n) {
             const int v = pl->fgroups[pl->inst_group[i]].v;
             std::vector<ItemDesc> one{fine_item(i, n)};
-            layout(one, fine_info(v), v == 1, 8);
+            layout(one, fine_info(v), v == 1, 8, 0, pr::fine_occupancy(v));
             pl->slice_index[pl->slice_base[i] + n] = (int)sl.size();
             pl->slice_blocks.push_back(one[0].nblocks);
             pl->slice_var.push_back(v);
@@ -832,7 +849,7 @@ int build_tables(pr_plan *pl)
             }
             std::stable_sort(items.begin(), items.end(),
                              [](const ItemDesc &a, const ItemDesc &b) { return a.nsteps > b.nsteps; });
-            const int nb = layout(items, cvi, cref, 4, pl->coarse_bpc);
+            const int nb = layout(items, cvi, cref, 4, pl->coarse_bpc, pr::coarse_occupancy(pl->coarse_v));
             pl->coarse_blocks[par * Pmax + n] = nb;
             pl->coarse_cnt[n] = (int)items.size();
             pl->coarse_nch[n] = items.empty() ? 0 : (items[0].nsteps + S - 1) / S;
@@ -1587,7 +1604,7 @@ int pr_autotune(const pr_problem *prob, int32_t dtype, int32_t batch, int32_t wh
     float best = 1e30f;
     Choice bestc;
     const int nv = which == 0 ? pr::fine_variant_count() : pr::coarse_variant_count();
-    static const int kBpc[] = {1, 2, 4};
+    static const int kBpc[] = {0, 1, 2, 4};   // 0: the resident blocks per compute unit
     for (int v = 2; v < nv && rc == PR_OK; ++v) {
         const bool ok = which == 0 ? fine_applicable(v, dtype, p.fine_order, p) : coarse_applicable(v, dtype, p);
         if (!ok) continue;
@@ -1647,7 +1664,7 @@ int pr_plan_autotune(pr_plan *pl, void *stream, int32_t *fine_variant, int32_t *
     hipEvent_t e0, e1;
     HIPCHK(hipEventCreate(&e0));
     HIPCHK(hipEventCreate(&e1));
-    static const int kBpc[] = {1, 2, 4};
+    static const int kBpc[] = {0, 1, 2, 4};   // 0: the resident blocks per compute unit
     std::vector<Choice> saved_f;
     for (const auto &g : pl->fgroups) saved_f.push_back(Choice{g.v, g.bpc});
     const Choice saved_g{pl->coarse_v, pl->coarse_bpc};

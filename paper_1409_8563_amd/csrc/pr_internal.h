@@ -71,6 +71,8 @@ int fine_variant_count();
 const VariantInfo *fine_variant(int v);      // v >= 2
 int coarse_variant_count();
 const VariantInfo *coarse_variant(int v);    // v >= 2
+int fine_occupancy(int v);                   // resident blocks per compute unit (1 if v < 2)
+int coarse_occupancy(int v);
 
 // Grid transfers of the coarsened G over tables of ItemDesc (src0 -> dst,
 // nx/ny/nz of the fine grid): injection to the grid coarsened by 2, and

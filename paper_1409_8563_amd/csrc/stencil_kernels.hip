@@ -16,6 +16,7 @@
 // fields.
 #include "pr_internal.h"
 
+#include <mutex>
 #include <utility>
 
 namespace pr {
@@ -1937,40 +1938,55 @@ __global__ void __launch_bounds__(kRefThreads)
 // ---------------------------------------------------------------------------
 // Variant registry
 // ---------------------------------------------------------------------------
-using FineLaunch = void (*)(const ItemDesc *, int, int, int, hipStream_t);
-using CoarseLaunch = void (*)(const ItemDesc *, int, int, int, hipStream_t);
+// A launch function launches its kernel, or with occ != nullptr only stores
+// the kernel's resident blocks per compute unit in *occ.
+using FineLaunch = void (*)(const ItemDesc *, int, int, int, hipStream_t, int *);
+using CoarseLaunch = void (*)(const ItemDesc *, int, int, int, hipStream_t, int *);
+
+template <typename K>
+void occupancy_of(K kernel, int threads, int *occ)
+{
+    int n = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, kernel, threads, 0) != hipSuccess || n < 1) n = 1;
+    *occ = n;
+}
 
 template <typename T, int R, int NXP, int NY, int BXT, int BY>
-void fine_launch(const ItemDesc *items, int nitems, int nblocks, int jstep, hipStream_t s)
+void fine_launch(const ItemDesc *items, int nitems, int nblocks, int jstep, hipStream_t s, int *occ)
 {
+    if (occ) return occupancy_of((rk4_step_fused<T, R, NXP, NY, BXT, BY>), BXT * BY, occ);
     hipLaunchKernelGGL((rk4_step_fused<T, R, NXP, NY, BXT, BY>), dim3(nblocks), dim3(BXT * BY), 0, s, items,
                        nitems, jstep);
 }
 
 template <typename T, int NXP, int NY, int BXT, int BY, int PD>
-void fine_launch_1b(const ItemDesc *items, int nitems, int nblocks, int jstep, hipStream_t s)
+void fine_launch_1b(const ItemDesc *items, int nitems, int nblocks, int jstep, hipStream_t s, int *occ)
 {
+    if (occ) return occupancy_of((rk4_step_fused1b<T, NXP, NY, BXT, BY, PD>), BXT * BY, occ);
     hipLaunchKernelGGL((rk4_step_fused1b<T, NXP, NY, BXT, BY, PD>), dim3(nblocks), dim3(BXT * BY), 0, s, items,
                        nitems, jstep);
 }
 
 template <typename T, int NXP, int NY, int BXT, int BY, int PD, int PAD>
-void fine_launch_1c(const ItemDesc *items, int nitems, int nblocks, int jstep, hipStream_t s)
+void fine_launch_1c(const ItemDesc *items, int nitems, int nblocks, int jstep, hipStream_t s, int *occ)
 {
+    if (occ) return occupancy_of((rk4_step_fused1c<T, NXP, NY, BXT, BY, PD, PAD>), BXT * BY, occ);
     hipLaunchKernelGGL((rk4_step_fused1c<T, NXP, NY, BXT, BY, PD, PAD>), dim3(nblocks), dim3(BXT * BY), 0, s, items,
                        nitems, jstep);
 }
 
 template <typename T, int S, int NXP, int NY, int BXT, int BY, int PD>
-void coarse_launch_1b(const ItemDesc *items, int nitems, int nblocks, int chunk, hipStream_t s)
+void coarse_launch_1b(const ItemDesc *items, int nitems, int nblocks, int chunk, hipStream_t s, int *occ)
 {
+    if (occ) return occupancy_of((euler_chunk_fused1b<T, S, NXP, NY, BXT, BY, PD>), BXT * BY, occ);
     hipLaunchKernelGGL((euler_chunk_fused1b<T, S, NXP, NY, BXT, BY, PD>), dim3(nblocks), dim3(BXT * BY), 0, s, items,
                        nitems, chunk);
 }
 
 template <typename T, int S, int NXP, int NY, int BXT, int BY>
-void coarse_launch(const ItemDesc *items, int nitems, int nblocks, int chunk, hipStream_t s)
+void coarse_launch(const ItemDesc *items, int nitems, int nblocks, int chunk, hipStream_t s, int *occ)
 {
+    if (occ) return occupancy_of((euler_chunk_fused<T, S, NXP, NY, BXT, BY>), BXT * BY, occ);
     hipLaunchKernelGGL((euler_chunk_fused<T, S, NXP, NY, BXT, BY>), dim3(nblocks), dim3(BXT * BY), 0, s, items,
                        nitems, chunk);
 }
@@ -1991,8 +2007,9 @@ struct CoarseEntry {
     FineEntry{VariantInfo{NAME, DT, 2, BXT * NXP - 8, BY * NY - 8, NXP, BXT * BY, 1},                  \
               &fine_launch_1b<T, NXP, NY, BXT, BY, PD>}
 template <typename T, int S, int NXP, int NY, int BXT, int BY, int PD>
-void coarse_launch_1c(const ItemDesc *items, int nitems, int nblocks, int chunk, hipStream_t s)
+void coarse_launch_1c(const ItemDesc *items, int nitems, int nblocks, int chunk, hipStream_t s, int *occ)
 {
+    if (occ) return occupancy_of((euler_chunk_fused1c<T, S, NXP, NY, BXT, BY, PD>), BXT * BY, occ);
     hipLaunchKernelGGL((euler_chunk_fused1c<T, S, NXP, NY, BXT, BY, PD>), dim3(nblocks), dim3(BXT * BY), 0, s, items,
                        nitems, chunk);
 }
@@ -2000,8 +2017,9 @@ void coarse_launch_1c(const ItemDesc *items, int nitems, int nblocks, int chunk,
     CoarseEntry{VariantInfo{NAME, DT, 0, BXT * NXP - 2 * S, BY * NY - 2 * S, NXP, BXT * BY, S},          \
                 &coarse_launch_1c<T, S, NXP, NY, BXT, BY, PD>}
 template <typename T, int NXP, int NY, int NW, int PD>
-void fine_launch_rows(const ItemDesc *items, int nitems, int nblocks, int jstep, hipStream_t s)
+void fine_launch_rows(const ItemDesc *items, int nitems, int nblocks, int jstep, hipStream_t s, int *occ)
 {
+    if (occ) return occupancy_of((rk4_step_rows<T, NXP, NY, NW, PD>), 64 * NW, occ);
     hipLaunchKernelGGL((rk4_step_rows<T, NXP, NY, NW, PD>), dim3(nblocks), dim3(64 * NW), 0, s, items, nitems,
                        jstep);
 }
@@ -2012,8 +2030,9 @@ void fine_launch_rows(const ItemDesc *items, int nitems, int nblocks, int jstep,
     FineEntry{VariantInfo{NAME, DT, 2, BXT * NXP - 8, BY * NY - 8, NXP, BXT * BY, 1},                  \
               &fine_launch_1c<T, NXP, NY, BXT, BY, PD, PAD>}
 template <typename T, int S, int NXP, int NY, int NW, int PD>
-void coarse_launch_rows(const ItemDesc *items, int nitems, int nblocks, int chunk, hipStream_t s)
+void coarse_launch_rows(const ItemDesc *items, int nitems, int nblocks, int chunk, hipStream_t s, int *occ)
 {
+    if (occ) return occupancy_of((euler_chunk_rows<T, S, NXP, NY, NW, PD>), 64 * NW, occ);
     hipLaunchKernelGGL((euler_chunk_rows<T, S, NXP, NY, NW, PD>), dim3(nblocks), dim3(64 * NW), 0, s, items, nitems,
                        chunk);
 }
@@ -2056,6 +2075,9 @@ const FineEntry kFine[] = {
     FINE_1B(float, 1, 2, 2, 36, 20, 2, "rk4b_f32_t64x32_p2x2_d2"),
     FINE_1B(float, 1, 2, 2, 36, 20, 4, "rk4b_f32_t64x32_p2x2_d4"),
     FINE_1B(float, 1, 4, 1, 18, 40, 2, "rk4b_f32_t64x32_p4x1_d2"),
+    FINE_1B(float, 1, 2, 2, 28, 16, 2, "rk4b_f32_t48x24_p2x2_d2"),
+    FINE_1B(float, 1, 2, 2, 28, 20, 2, "rk4b_f32_t48x32_p2x2_d2"),
+    FINE_1B(float, 1, 2, 2, 36, 16, 2, "rk4b_f32_t64x24_p2x2_d2"),
     FINE_1C(double, 2, 1, 2, 40, 20, 2, 2, "rk4c_f64_t32x32_p1x2_pad2"),
     FINE_1C(double, 2, 1, 2, 40, 20, 2, 6, "rk4c_f64_t32x32_p1x2_pad6"),
     FINE_1C(double, 2, 2, 2, 20, 20, 2, 2, "rk4c_f64_t32x32_p2x2_pad2"),
@@ -2130,6 +2152,30 @@ const VariantInfo *coarse_variant(int v)
     return &kCoarse[v - 2].info;
 }
 
+// Resident blocks per compute unit of a fused variant on the current device
+// (queried once per variant; 1 for anything else).
+int fine_occupancy(int v)
+{
+    static std::mutex mu;
+    static int cache[kNumFine] = {};
+    if (v < 2 || v >= kNumFine + 2) return 1;
+    std::lock_guard<std::mutex> lk(mu);
+    int &c = cache[v - 2];
+    if (c == 0) kFine[v - 2].fn(nullptr, 0, 0, 0, nullptr, &c);
+    return c;
+}
+
+int coarse_occupancy(int v)
+{
+    static std::mutex mu;
+    static int cache[kNumCoarse] = {};
+    if (v < 2 || v >= kNumCoarse + 2) return 1;
+    std::lock_guard<std::mutex> lk(mu);
+    int &c = cache[v - 2];
+    if (c == 0) kCoarse[v - 2].fn(nullptr, 0, 0, 0, nullptr, &c);
+    return c;
+}
+
 hipError_t launch_fine_step(int variant, int dtype, int order, const ItemDesc *items, int nitems, int nblocks,
                             int jstep, hipStream_t s)
 {
@@ -2155,7 +2201,7 @@ hipError_t launch_fine_step(int variant, int dtype, int order, const ItemDesc *i
         return hipGetLastError();
     }
     if (variant < 2 || variant >= kNumFine + 2) return hipErrorInvalidValue;
-    kFine[variant - 2].fn(items, nitems, nblocks, jstep, s);
+    kFine[variant - 2].fn(items, nitems, nblocks, jstep, s, nullptr);
     return hipGetLastError();
 }
 
@@ -2171,7 +2217,7 @@ hipError_t launch_coarse_chunk(int variant, int dtype, const ItemDesc *items, in
         return hipGetLastError();
     }
     if (variant < 2 || variant >= kNumCoarse + 2) return hipErrorInvalidValue;
-    kCoarse[variant - 2].fn(items, nitems, nblocks, chunk, s);
+    kCoarse[variant - 2].fn(items, nitems, nblocks, chunk, s, nullptr);
     return hipGetLastError();
 }
 

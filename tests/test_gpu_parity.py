@@ -515,7 +515,7 @@ def test_plan_autotune_keeps_results(pr):
         before, blog = plan.solve(u0s)
         before = [host(x) for x in before]
         choice = plan.autotune()
-        assert choice["fine"][1] in (1, 2, 4) and choice["coarse"][1] in (1, 2, 4)
+        assert choice["fine"][1] in (0, 1, 2, 4) and choice["coarse"][1] in (0, 1, 2, 4)
         for rep in range(2):
             after, alog = plan.solve(u0s)
             for i in range(len(probs)):
