@@ -202,7 +202,9 @@ size_t pr_defect_workspace_bytes(int32_t batch);
  * F variant chosen for its own grid (tuned, else built-in, at the batch of
  * all slices of the instances with that grid); instances with the same
  * choice form a launch group, and every fine step is one launch per group.
- * G uses one variant for all instances.
+ * With several groups, the groups' launches of an F phase run concurrently
+ * on streams owned by the plan, forked from and joined back to the solve's
+ * stream.  G uses one variant for all instances.
  */
 size_t pr_plan_workspace_bytes(const pr_problem *probs, int32_t ninst, int32_t mode);
 int pr_plan_create(const pr_problem *probs, int32_t ninst, int32_t mode, void *ws, size_t ws_bytes,

@@ -554,6 +554,12 @@ struct pr_plan {
     };
     std::vector<FineGroup> fgroups;
     std::vector<int> inst_group;        // instance -> group
+    // groups 1.. run on their own streams, forked from and joined back to
+    // the solve's stream around every F phase (the groups' instances are
+    // disjoint, so their launches may overlap)
+    std::vector<hipStream_t> aux;
+    hipEvent_t fork_ev = nullptr;
+    std::vector<hipEvent_t> join_ev;
 
     // device tables
     ItemDesc *fine_tab = nullptr;       // per k and group: the group's items (batched layout)
@@ -936,11 +942,22 @@ int enqueue_init(pr_plan *pl, hipStream_t s)
 int enqueue_fine(pr_plan *pl, int k, hipStream_t s)
 {
     if (!pl->per_slice) {
-        for (const auto &g : pl->fgroups) {
-            const ItemDesc *tab = pl->fine_tab + g.off[k];
-            const std::vector<int> &act = g.active[k];
+        const int ng = (int)pl->fgroups.size();
+        if (ng > 1) {
+            HIPCHK(hipEventRecord(pl->fork_ev, s));
+            for (int g = 1; g < ng; ++g) HIPCHK(hipStreamWaitEvent(pl->aux[g - 1], pl->fork_ev, 0));
+        }
+        for (int g = 0; g < ng; ++g) {
+            const auto &gr = pl->fgroups[g];
+            hipStream_t sg = g == 0 ? s : pl->aux[g - 1];
+            const ItemDesc *tab = pl->fine_tab + gr.off[k];
+            const std::vector<int> &act = gr.active[k];
             for (int j = 0; j < (int)act.size(); ++j)
-                HIPCHK(pr::launch_fine_step(g.v, pl->dtype, pl->probs[0].fine_order, tab, g.cnt[k], act[j], j, s));
+                HIPCHK(pr::launch_fine_step(gr.v, pl->dtype, pl->probs[0].fine_order, tab, gr.cnt[k], act[j], j, sg));
+        }
+        for (int g = 1; g < ng; ++g) {
+            HIPCHK(hipEventRecord(pl->join_ev[g - 1], pl->aux[g - 1]));
+            HIPCHK(hipStreamWaitEvent(s, pl->join_ev[g - 1], 0));
         }
     } else {
         for (int i = 0; i < pl->ninst; ++i)
@@ -1297,6 +1314,21 @@ int pr_plan_create(const pr_problem *probs, int32_t ninst, int32_t mode, void *w
         delete pl;
         return rc;
     }
+    if (pl->fgroups.size() > 1 && !pl->per_slice) {
+        hipError_t er = hipEventCreateWithFlags(&pl->fork_ev, hipEventDisableTiming);
+        for (size_t g = 1; g < pl->fgroups.size() && er == hipSuccess; ++g) {
+            hipStream_t st = nullptr;
+            hipEvent_t e = nullptr;
+            er = hipStreamCreateWithFlags(&st, hipStreamNonBlocking);
+            if (er == hipSuccess) pl->aux.push_back(st);
+            if (er == hipSuccess) er = hipEventCreateWithFlags(&e, hipEventDisableTiming);
+            if (er == hipSuccess) pl->join_ev.push_back(e);
+        }
+        if (er != hipSuccess) {
+            pr_plan_destroy(pl);
+            return fail(PR_EDEVICE, "stream or event creation failed: %s", hipGetErrorString(er));
+        }
+    }
     if (pl->timed) {
         pl->ev.resize(3 + 3 * std::max(pl->K, 1));
         for (auto &e : pl->ev) {
@@ -1319,6 +1351,9 @@ void pr_plan_destroy(pr_plan *plan)
     for (auto &e : plan->ev)
         if (e) (void)hipEventDestroy(e);
     if (plan->own) (void)hipStreamDestroy(plan->own);
+    for (auto st : plan->aux) (void)hipStreamDestroy(st);
+    for (auto e : plan->join_ev) (void)hipEventDestroy(e);
+    if (plan->fork_ev) (void)hipEventDestroy(plan->fork_ev);
     delete plan;
 }
 
