@@ -1275,6 +1275,10 @@ int pr_plan_create(const pr_problem *probs, int32_t ninst, int32_t mode, void *w
             c = pick_fine(probs[i], pl->dtype, batch);
             if (c.v < 1 || !fine_applicable(c.v, pl->dtype, probs[i].fine_order, probs[i]))
                 c = Choice{pick_fine_default(probs[i], pl->dtype, batch), 0};
+            if (c.v < 1) {
+                delete pl;
+                return fail(PR_EUNSUPPORTED, "instance %d: no fine kernel variant for this grid", i);
+            }
         }
         int g = 0;
         while (g < (int)pl->fgroups.size() && !(pl->fgroups[g].v == c.v && pl->fgroups[g].bpc == c.bpc)) ++g;
