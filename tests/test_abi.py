@@ -196,6 +196,54 @@ def test_variant_registry():
     assert L.lib().pr_set_kernel_variant(0, 0) == 0
 
 
+@pytest.mark.parametrize("n3,dtype,batch,name", [
+    ((128, 128, 128), 2, 16, "rk4w_f64_x128_y8_p2x1_w16"),
+    ((64, 64, 64), 2, 8, "rk4w_f64_x64_y8_p1x1_w16"),
+    ((40, 36, 20), 2, 4, "rk4b_f64_t32x32_p1x2_d2"),
+    ((256, 256, 256), 1, 32, "rk4w_f32_x256_y8_p4x2_w8"),
+    ((128, 128, 128), 1, 136, "rk4w_f32_x128_y16_p2x3_w8"),
+    ((128, 128, 128), 1, 1, "rk4w_f32_x128_y8_p2x1_w16"),
+    ((96, 96, 96), 1, 88, "rk4b_f32_t48x32_p2x2_d2"),
+    ((64, 64, 64), 1, 152, "rk4b_f32_t64x32_p2x2_d2"),
+    ((48, 48, 48), 1, 136, "rk4b_f32_t48x24_p2x2_d2"),
+    ((512, 512, 512), 1, 32, "rk4b_f32_t64x32_p2x2_d2"),
+    ((37, 29, 23), 1, 2, "rk4b_f32_t32x32_p1x4_d2"),
+])
+def test_builtin_fine_kernel_choice(n3, dtype, batch, name):
+    """Host logic, no device: the built-in F kernel for a grid (whole-row for
+    n_x = 64/128/256 as measured; for other FP32 grids the 2-D tile that
+    computes the fewest points per output point)."""
+    import paper_1409_8563_amd as pr
+    p = W.small_problem(n=n3, P=2, nf=4)
+    p.flags |= W.ALLOW_UNSTABLE
+    assert pr.sweep_kernel_variant(p, dtype, batch, 0) == name
+
+
+def test_fp32_tile_choice_minimises_computed_points():
+    """For even FP32 grids without a whole-row kernel the chosen tile has the
+    fewest computed points per output point (4-point halo per side) among the
+    four two-point tiles."""
+    import paper_1409_8563_amd as pr
+    cands = {v["name"]: v for v in pr.variants(0)
+             if v["name"] in ("rk4b_f32_t64x32_p2x2_d2", "rk4b_f32_t64x24_p2x2_d2",
+                              "rk4b_f32_t48x32_p2x2_d2", "rk4b_f32_t48x24_p2x2_d2")}
+    assert len(cands) == 4
+
+    def waste(v, nx, ny):
+        tx, ty = v["tile"]
+        return (-(-nx // tx) * (tx + 8) / nx) * (-(-ny // ty) * (ty + 8) / ny)
+
+    for nx in range(8, 200, 6):
+        for ny in (10, 24, 48, 72, 100):
+            if nx in (128, 256):
+                continue
+            p = W.small_problem(n=(nx, ny, 12), P=2, nf=4)
+            p.flags |= W.ALLOW_UNSTABLE
+            got = pr.sweep_kernel_variant(p, 1, 4, 0)
+            assert got in cands, (nx, ny, got)
+            assert waste(cands[got], nx, ny) <= min(waste(v, nx, ny) for v in cands.values()) * (1 + 1e-12)
+
+
 def test_whole_row_variant_rejects_other_nx():
     """A forced whole-row variant on a grid whose n_x it does not cover is
     refused before any launch."""

@@ -452,8 +452,13 @@ def test_multi_instance_launch_groups(pr, orc):
             for i, p in enumerate(probs):
                 U, _ = orc.parareal(p, u0s[i], K=p.K)
                 assert rel_l2(singles[i], U[-1]) <= FP64_TOL, i
-        for extra in (0, pr.PR_MODE_PER_SLICE, pr.PR_MODE_GRAPH):
-            plan = pr.Plan(probs, mode | extra)
+        # skipping converged slices and early stopping at tol = 0 change no bit
+        skip_early = [W.Problem(**{**p.__dict__, "flags": p.flags | W.SKIP_CONVERGED | W.EARLY_STOP})
+                      for p in probs]
+        for extra, ps in ((0, probs), (pr.PR_MODE_PER_SLICE, probs), (pr.PR_MODE_GRAPH, probs),
+                          (pr.PR_MODE_TIMED, probs), (0, skip_early)):
+            say("launch groups", mode, extra, ps[0].flags)
+            plan = pr.Plan(ps, mode | extra)
             groups = plan.fine_groups()
             assert len(groups) == 2 and sorted(g[2] for g in groups) == [1, 2], groups
             assert any(g[0].startswith("rk4w_") for g in groups), groups
@@ -461,7 +466,7 @@ def test_multi_instance_launch_groups(pr, orc):
                 if rep == 1:
                     plan.autotune()
                 uT, _ = plan.solve([cuda(u) for u in u0s])
-                for i in range(len(probs)):
+                for i in range(len(ps)):
                     assert np.array_equal(host(uT[i]), singles[i]), (mode, extra, rep, i)
 
 
