@@ -656,8 +656,9 @@ def test_full_size_c4_batched(pr):
     probs = [p for p, _ in insts]
     say("c4 batched: %d instances" % len(probs))
     u0s = [cuda(W.synth_u0(p.n, m)) for p, m in insts]
-    # one F launch per step over all slices of all instances, tuned tiles and
-    # z chunks, the whole solve replayed from a recorded graph
+    # per fine step one launch per kernel group over all slices of its
+    # instances (groups concurrent), tuned tiles and z chunks, the whole
+    # solve replayed from a recorded graph
     plan = pr.Plan(probs, pr.PR_MODE_MIXED | pr.PR_MODE_GRAPH)
     say("c4 tuned", plan.autotune())
     uT, log = plan.solve(u0s)
