@@ -1148,6 +1148,9 @@ __global__ void __launch_bounds__(64 * NW)
         }(std::make_integer_sequence<int, L>{});
     };
     if (act4) {
+        // with two wavefronts per SIMD, the wavefronts that run all four
+        // stages issue first; the partner wavefront (fewer stages) fills in
+        if constexpr (NW <= 8) __builtin_amdgcn_s_setprio(1);
         int pb = 0;
         for (; pb < niter && pb < 2 * L; pb += L) trip(pb, std::false_type{});
         for (; pb < niter; pb += L) trip(pb, std::true_type{});
