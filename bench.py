@@ -141,8 +141,8 @@ def main():
                     help="run one plain device-to-device copy of this size first (calibrates HBM counters)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py measures one GPU only: this build has no multi-GPU path (time slices would shard "
-              "over xGMI; see the design notes). Run with --gpus 1.", file=sys.stderr)
+        print("bench.py measures one GPU only: there is no multi-GPU path (the time slices would shard "
+              "across GPUs, with the coarse-chain hand-off sent over xGMI). Run with --gpus 1.", file=sys.stderr)
         sys.exit(2)
 
     import numpy as np

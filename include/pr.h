@@ -51,7 +51,7 @@ extern "C" {
 #define PR_EUNSTABLE    -2  /* explicit step outside its stability bound (see pr_check_stability) */
 #define PR_ENOMEM       -3  /* workspace smaller than the queried size */
 #define PR_EDEVICE      -4  /* HIP runtime failure or no device */
-#define PR_EUNSUPPORTED -5  /* valid request this build does not implement */
+#define PR_EUNSUPPORTED -5  /* valid request the library does not implement */
 #define PR_ENONFINITE   -6  /* a defect norm became NaN or Inf during a solve */
 
 /* dtypes of fields */

@@ -18,7 +18,7 @@
  *     interpolation                                    (Section 2.2.2, speedup-bound discussion)
  *   - norms of the defect                              (Section 2.2.3, eq. defect)
  *
- * Readings taken where the paper is silent (listed in the design notes):
+ * Readings taken where the paper is silent:
  *   - grid points x_i = i/n, periodic, h_d = 1/n_d, storage u[(z*ny + y)*nx + x];
  *   - RK4 stage times t, t+dt/2, t+dt/2, t+dt (or all t with nu_frozen);
  *   - fine step j of the whole run starts at t = j*dt (slice n, local step i:
