@@ -280,7 +280,7 @@ int pick_fine_default(const pr_problem &p, int dtype, int batch)
     if (dtype == PR_FP64)
         name = order == 4 ? (even ? "rk4_f64_o4_t32x16_p2x1" : "rk4_f64_o4_t24x8_p1x1")
                : p.n[0] == 128 ? "rk4w_f64_x128_y8_p2x1_w16"
-               : p.n[0] == 64  ? "rk4w_f64_x64_y8_p1x1_w16"
+               : p.n[0] == 64  ? (batch >= 4 ? "rk4w_f64_x64_y16_p1x2_w12" : "rk4w_f64_x64_y8_p1x2_w8")
                                : "rk4b_f64_t32x32_p1x2_d2";
     else if (order == 2 && even && p.n[0] != 256 && p.n[0] != 128) {
         // two x points per thread, tiled: the tile that computes the fewest
@@ -304,7 +304,7 @@ int pick_fine_default(const pr_problem &p, int dtype, int batch)
     } else
         name = order == 4 ? (even ? "rk4_f32_o4_t32x16_p2x2" : "rk4_f32_o4_t32x16_p1x2")
                : p.n[0] == 256 ? "rk4w_f32_x256_y8_p4x2_w8"
-               : p.n[0] == 128 ? (batch >= 4 ? "rk4w_f32_x128_y16_p2x3_w8" : "rk4w_f32_x128_y8_p2x1_w16")
+               : p.n[0] == 128 ? (batch >= 4 ? "rk4w_f32_x128_y16_p2x2_w12" : "rk4w_f32_x128_y8_p2x2_w8")
                                : "rk4b_f32_t32x32_p1x4_d2";
     return find_fine(name);
 }

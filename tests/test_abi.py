@@ -198,11 +198,12 @@ def test_variant_registry():
 
 @pytest.mark.parametrize("n3,dtype,batch,name", [
     ((128, 128, 128), 2, 16, "rk4w_f64_x128_y8_p2x1_w16"),
-    ((64, 64, 64), 2, 8, "rk4w_f64_x64_y8_p1x1_w16"),
+    ((64, 64, 64), 2, 8, "rk4w_f64_x64_y16_p1x2_w12"),
+    ((64, 64, 64), 2, 1, "rk4w_f64_x64_y8_p1x2_w8"),
     ((40, 36, 20), 2, 4, "rk4b_f64_t32x32_p1x2_d2"),
     ((256, 256, 256), 1, 32, "rk4w_f32_x256_y8_p4x2_w8"),
-    ((128, 128, 128), 1, 136, "rk4w_f32_x128_y16_p2x3_w8"),
-    ((128, 128, 128), 1, 1, "rk4w_f32_x128_y8_p2x1_w16"),
+    ((128, 128, 128), 1, 136, "rk4w_f32_x128_y16_p2x2_w12"),
+    ((128, 128, 128), 1, 1, "rk4w_f32_x128_y8_p2x2_w8"),
     ((96, 96, 96), 1, 88, "rk4b_f32_t48x32_p2x2_d2"),
     ((64, 64, 64), 1, 152, "rk4b_f32_t64x32_p2x2_d2"),
     ((48, 48, 48), 1, 136, "rk4b_f32_t48x24_p2x2_d2"),
