@@ -282,6 +282,8 @@ int pick_fine_default(const pr_problem &p, int dtype, int batch)
                : p.n[0] == 128 ? "rk4w_f64_x128_y8_p2x1_w16"
                : p.n[0] == 64  ? (batch >= 4 ? "rk4w_f64_x64_y16_p1x2_w12" : "rk4w_f64_x64_y8_p1x2_w8")
                                : "rk4b_f64_t32x32_p1x2_d2";
+    else if (order == 2 && p.n[0] == 64)
+        name = batch >= 64 ? "rk4w_f32_x64_y24_p1x2_w16" : "rk4w_f32_x64_y16_p1x2_w12";
     else if (order == 2 && even && p.n[0] != 256 && p.n[0] != 128) {
         // two x points per thread, tiled: the tile that computes the fewest
         // points per output point of this grid in x and y (halo of 4 per side)
@@ -373,14 +375,14 @@ void fill_item(ItemDesc &it, const pr_problem &p, bool fine)
 }
 
 // Tile layout of a launch: tiles per item, z chunks and block ranges
-// (assigned in item order); returns the total number of blocks.  occ =
-// resident blocks per compute unit of the variant; bpc = blocks per compute
-// unit that the z chunking aims for (0: occ).
-int layout(std::vector<ItemDesc> &items, const VariantInfo *vi, bool ref, int zmin, int bpc, int occ)
+// (assigned in item order); returns the total number of blocks.  Chunks are
+// at least zmin planes deep; a block walks its chunk plus `fill` planes of
+// pipeline fill.  occ = resident blocks per compute unit of the variant;
+// bpc = resident blocks per compute unit to assume instead (0: occ).
+int layout(std::vector<ItemDesc> &items, const VariantInfo *vi, bool ref, int zmin, int fill, int bpc, int occ)
 {
     const int cus = std::max(g_num_cus, 1);
-    const int64_t target = (int64_t)(bpc > 0 ? bpc : std::max(occ, 1)) * cus;
-    const int64_t cap = (int64_t)std::max(occ, 1) * cus;
+    const int64_t cap = (int64_t)(bpc > 0 ? bpc : std::max(occ, 1)) * cus;
     if (ref) {
         int b = 0;
         for (auto &it : items) {
@@ -394,29 +396,28 @@ int layout(std::vector<ItemDesc> &items, const VariantInfo *vi, bool ref, int zm
         return b;
     }
     int64_t bxy = 0;
+    int nzmax = 1;
     for (auto &it : items) {
         it.tiles_x = (it.nx + vi->tx - 1) / vi->tx;
         it.tiles_y = (it.ny + vi->ty - 1) / vi->ty;
         bxy += (int64_t)it.tiles_x * it.tiles_y;
+        nzmax = std::max(nzmax, it.nz);
     }
-    int want = (int)std::max<int64_t>(1, (target + bxy - 1) / std::max<int64_t>(bxy, 1));
-    // Enough tiles for the target at one z chunk per tile: the launch runs in
-    // rounds of `cap` resident blocks.  Take the chunk count (up to 4) with
-    // the fewest rounds x planes per block (chunk depth plus the 8-plane
-    // pipeline fill), so that a last, partly filled round of full-depth
-    // blocks is traded for shorter blocks when that is cheaper.
-    if (bxy >= target) {
-        int nzmax = 1;
-        for (const auto &it : items) nzmax = std::max(nzmax, it.nz);
-        int64_t best = INT64_MAX;
-        for (int zc = 1; zc <= 4; ++zc) {
-            if (zc > 1 && nzmax / zc < zmin) break;
-            const int64_t rounds = (bxy * zc + cap - 1) / cap;
-            const int64_t cost = rounds * ((nzmax + zc - 1) / zc + 8);
-            if (cost < best) {
-                best = cost;
-                want = zc;
-            }
+    // The launch runs in rounds of `cap` resident blocks, each taking time in
+    // proportion to the planes it walks.  Take the chunk count with the
+    // fewest rounds x planes per block: enough chunks to fill the device, and
+    // no last, mostly empty round of long blocks.
+    int want = 1;
+    int64_t best = INT64_MAX;
+    const int zcmax = std::max(1, nzmax / zmin);
+    for (int zc = 1; zc <= zcmax; ++zc) {
+        const int tz = (nzmax + zc - 1) / zc;
+        if ((nzmax + tz - 1) / tz != zc) continue;   // the layout of a smaller count
+        const int64_t rounds = (bxy * zc + cap - 1) / cap;
+        const int64_t cost = rounds * (tz + fill);
+        if (cost < best) {
+            best = cost;
+            want = zc;
         }
     }
     int b = 0;
@@ -500,8 +501,9 @@ int sweep_common(const pr_problem *prob_in, int dtype, int batch, const void *u_
     }
     const VariantInfo *vi = fine ? fine_info(v) : coarse_info(v);
     const int zmin = fine ? 8 : 4;
+    const int fill = fine ? 8 : 2 * coarse_steps_per_launch(v);
     const int occ = fine ? pr::fine_occupancy(v) : pr::coarse_occupancy(v);
-    const int nblocks = layout(items, vi, ref, zmin, ch.bpc, occ);
+    const int nblocks = layout(items, vi, ref, zmin, fill, ch.bpc, occ);
     HIPCHK(pr::launch_write_items(items.data(), batch, table, s));
     if (fine) {
         for (int j = 0; j < nsteps; ++j)
@@ -778,7 +780,7 @@ int build_tables(pr_plan *pl)
                 for (int n = (pl->skip ? k : 0); n < pl->inst[i].P; ++n) items.push_back(fine_item(i, n));
             std::stable_sort(items.begin(), items.end(),
                              [](const ItemDesc &a, const ItemDesc &b) { return a.nsteps > b.nsteps; });
-            layout(items, fine_info(g.v), g.v == 1, 8, g.bpc, pr::fine_occupancy(g.v));
+            layout(items, fine_info(g.v), g.v == 1, 8, 8, g.bpc, pr::fine_occupancy(g.v));
             const int maxsteps = items.empty() ? 0 : items[0].nsteps;
             std::vector<int> act(maxsteps, 0);
             for (int j = 0; j < maxsteps; ++j) {
@@ -804,7 +806,7 @@ int build_tables(pr_plan *pl)
         for (int n = 0; n < pl->inst[i].P; ++n) {
             const int v = pl->fgroups[pl->inst_group[i]].v;
             std::vector<ItemDesc> one{fine_item(i, n)};
-            layout(one, fine_info(v), v == 1, 8, 0, pr::fine_occupancy(v));
+            layout(one, fine_info(v), v == 1, 8, 8, 0, pr::fine_occupancy(v));
             pl->slice_index[pl->slice_base[i] + n] = (int)sl.size();
             pl->slice_blocks.push_back(one[0].nblocks);
             pl->slice_var.push_back(v);
@@ -855,7 +857,7 @@ int build_tables(pr_plan *pl)
             }
             std::stable_sort(items.begin(), items.end(),
                              [](const ItemDesc &a, const ItemDesc &b) { return a.nsteps > b.nsteps; });
-            const int nb = layout(items, cvi, cref, 4, pl->coarse_bpc, pr::coarse_occupancy(pl->coarse_v));
+            const int nb = layout(items, cvi, cref, 4, 2 * S, pl->coarse_bpc, pr::coarse_occupancy(pl->coarse_v));
             pl->coarse_blocks[par * Pmax + n] = nb;
             pl->coarse_cnt[n] = (int)items.size();
             pl->coarse_nch[n] = items.empty() ? 0 : (items[0].nsteps + S - 1) / S;

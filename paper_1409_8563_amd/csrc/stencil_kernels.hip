@@ -2103,6 +2103,8 @@ const FineEntry kFine[] = {
     FINE_ROWS(float, 1, 2, 2, 8, 2, "rk4w_f32_x128_y8_p2x2_w8"),
     FINE_ROWS(float, 1, 2, 3, 8, 2, "rk4w_f32_x128_y16_p2x3_w8"),
     FINE_ROWS(float, 1, 2, 2, 12, 2, "rk4w_f32_x128_y16_p2x2_w12"),
+    FINE_ROWS(float, 1, 1, 2, 12, 2, "rk4w_f32_x64_y16_p1x2_w12"),
+    FINE_ROWS(float, 1, 1, 2, 16, 2, "rk4w_f32_x64_y24_p1x2_w16"),
     FINE_ROWS(double, 2, 1, 2, 12, 2, "rk4w_f64_x64_y16_p1x2_w12"),
 };
 

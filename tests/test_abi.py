@@ -205,7 +205,8 @@ def test_variant_registry():
     ((128, 128, 128), 1, 136, "rk4w_f32_x128_y16_p2x2_w12"),
     ((128, 128, 128), 1, 1, "rk4w_f32_x128_y8_p2x2_w8"),
     ((96, 96, 96), 1, 88, "rk4b_f32_t48x32_p2x2_d2"),
-    ((64, 64, 64), 1, 152, "rk4b_f32_t64x32_p2x2_d2"),
+    ((64, 64, 64), 1, 152, "rk4w_f32_x64_y24_p1x2_w16"),
+    ((64, 64, 64), 1, 16, "rk4w_f32_x64_y16_p1x2_w12"),
     ((48, 48, 48), 1, 136, "rk4b_f32_t48x24_p2x2_d2"),
     ((512, 512, 512), 1, 32, "rk4b_f32_t64x32_p2x2_d2"),
     ((37, 29, 23), 1, 2, "rk4b_f32_t32x32_p1x4_d2"),
@@ -236,7 +237,7 @@ def test_fp32_tile_choice_minimises_computed_points():
 
     for nx in range(8, 200, 6):
         for ny in (10, 24, 48, 72, 100):
-            if nx in (128, 256):
+            if nx in (64, 128, 256):
                 continue
             p = W.small_problem(n=(nx, ny, 12), P=2, nf=4)
             p.flags |= W.ALLOW_UNSTABLE
