@@ -500,7 +500,7 @@ int sweep_common(const pr_problem *prob_in, int dtype, int batch, const void *u_
         it.nsteps = nsteps;
     }
     const VariantInfo *vi = fine ? fine_info(v) : coarse_info(v);
-    const int zmin = fine ? 8 : 4;
+    const int zmin = 2;
     const int fill = fine ? 8 : 2 * coarse_steps_per_launch(v);
     const int occ = fine ? pr::fine_occupancy(v) : pr::coarse_occupancy(v);
     const int nblocks = layout(items, vi, ref, zmin, fill, ch.bpc, occ);
@@ -780,7 +780,7 @@ int build_tables(pr_plan *pl)
                 for (int n = (pl->skip ? k : 0); n < pl->inst[i].P; ++n) items.push_back(fine_item(i, n));
             std::stable_sort(items.begin(), items.end(),
                              [](const ItemDesc &a, const ItemDesc &b) { return a.nsteps > b.nsteps; });
-            layout(items, fine_info(g.v), g.v == 1, 8, 8, g.bpc, pr::fine_occupancy(g.v));
+            layout(items, fine_info(g.v), g.v == 1, 2, 8, g.bpc, pr::fine_occupancy(g.v));
             const int maxsteps = items.empty() ? 0 : items[0].nsteps;
             std::vector<int> act(maxsteps, 0);
             for (int j = 0; j < maxsteps; ++j) {
@@ -806,7 +806,7 @@ int build_tables(pr_plan *pl)
         for (int n = 0; n < pl->inst[i].P; ++n) {
             const int v = pl->fgroups[pl->inst_group[i]].v;
             std::vector<ItemDesc> one{fine_item(i, n)};
-            layout(one, fine_info(v), v == 1, 8, 8, 0, pr::fine_occupancy(v));
+            layout(one, fine_info(v), v == 1, 2, 8, 0, pr::fine_occupancy(v));
             pl->slice_index[pl->slice_base[i] + n] = (int)sl.size();
             pl->slice_blocks.push_back(one[0].nblocks);
             pl->slice_var.push_back(v);
@@ -857,7 +857,7 @@ int build_tables(pr_plan *pl)
             }
             std::stable_sort(items.begin(), items.end(),
                              [](const ItemDesc &a, const ItemDesc &b) { return a.nsteps > b.nsteps; });
-            const int nb = layout(items, cvi, cref, 4, 2 * S, pl->coarse_bpc, pr::coarse_occupancy(pl->coarse_v));
+            const int nb = layout(items, cvi, cref, 2, 2 * S, pl->coarse_bpc, pr::coarse_occupancy(pl->coarse_v));
             pl->coarse_blocks[par * Pmax + n] = nb;
             pl->coarse_cnt[n] = (int)items.size();
             pl->coarse_nch[n] = items.empty() ? 0 : (items[0].nsteps + S - 1) / S;
