@@ -105,6 +105,19 @@ def per_config_rates(pr, W, torch, kernel_of):
                      "launch_us": round(ms * 1e3, 1), "kernel": "%s (%s)" % (kernel_of(fv), fv)}
         del u, o
         torch.cuda.empty_cache()
+    # the paper's own setup (Section 3.1): fourth-order F on 128^3 FP64, all
+    # 8 slices per launch
+    pp = W.paper_setup(100.0)
+    u = torch.randn((pp.P,) + tuple(reversed(pp.n)), dtype=torch.float64, device="cuda")
+    o = torch.empty_like(u)
+    ms = ev_time(lambda k: pr.fine_sweep(pp, u, [s * pp.nf for s in range(pp.P)], k, u_out=o), 32)
+    lups = pp.P * pp.npts
+    fv = pr.sweep_kernel_variant(pp, pr.PR_FP64, pp.P, 0)
+    out["paper_setup_order4_fp64"] = {"glups": round(lups / ms / 1e6, 1), "gbs": round(lups * 16 / ms / 1e6, 1),
+                                      "frac": round(lups * 16 / ms / 1e6 / HBM_PEAK_GBS, 4),
+                                      "launch_us": round(ms * 1e3, 1), "kernel": "%s (%s)" % (kernel_of(fv), fv)}
+    del u, o
+    torch.cuda.empty_cache()
     insts = W.batched_config(64)
     probs = [W.Problem(**{**q.__dict__, "K": 1}) for q, _ in insts]
     u0s = [torch.randn(tuple(reversed(q.n)), dtype=torch.float64, device="cuda") for q in probs]
