@@ -304,7 +304,7 @@ int pick_fine_default(const pr_problem &p, int dtype, int batch)
         }
         return best_v;
     } else
-        name = order == 4 ? (even ? "rk4_f32_o4_t32x16_p2x2" : "rk4_f32_o4_t32x16_p1x2")
+        name = order == 4 ? (even ? "rk4r_f32_o4_t32x16_p2x2_d2" : "rk4_f32_o4_t32x16_p1x2")
                : p.n[0] == 256 ? "rk4w_f32_x256_y8_p4x2_w8"
                : p.n[0] == 128 ? (batch >= 4 ? "rk4w_f32_x128_y16_p2x2_w12" : "rk4w_f32_x128_y8_p2x2_w8")
                                : "rk4b_f32_t32x32_p1x4_d2";

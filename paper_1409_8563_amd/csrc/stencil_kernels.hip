@@ -1159,6 +1159,229 @@ __global__ void __launch_bounds__(64 * NW)
     }
 }
 // ---------------------------------------------------------------------------
+// Fused RK4 step for stencils of radius R with one barrier per z plane.
+// Stage s evaluates plane p - sR in iteration p.  Each of the four stage
+// inputs has two LDS slots, chosen by iteration parity; in iteration p input
+// B (0..3) puts the plane that stage B+1 evaluates in iteration p+1, namely
+// p + 1 - (B+1)R.  For R >= 2 that plane was computed an iteration earlier,
+// so every put happens at the top of the iteration; for R = 1 it is the plane
+// just computed, put right after its stage.  One barrier per iteration orders
+// the puts of iteration p-1 before the reads of p, and the reads of p-1
+// before the puts of p.  In-plane neighbours at distance k <= R come from the
+// thread's own registers inside its NXP x NY group, else from LDS; z
+// neighbours from the register rings.
+// ---------------------------------------------------------------------------
+template <typename T, int R, int NXP, int NY, int BXT, int BY, int PD>
+__global__ void __launch_bounds__(BXT *BY)
+    rk4_step_fused1r(const ItemDesc *__restrict__ items, int nitems, int jstep)
+{
+    constexpr int H = 4 * R;
+    constexpr int EX = BXT * NXP, EY = BY * NY;
+    constexpr int TX = EX - 2 * H, TY = EY - 2 * H;
+    constexpr int L = (3 * R + 2) / 2 * 2;                 // z-ring length >= 3R+1, even
+    static_assert(L % PD == 0, "prefetch depth must divide the unroll");
+    constexpr int CO = ((R + NXP - 1) / NXP) * NXP;        // halo columns in LDS, whole groups
+    constexpr int LX = EX + 2 * CO + (sizeof(T) == 8 ? 2 : 4);
+    constexpr int LY = EY + 2 * R;
+    static_assert(TX > 0 && TY > 0, "tile too small for the halo");
+    __shared__ __align__(16) T lds[4][2][LY][LX];          // [stage input][slot][row][col]
+
+    const int lb = xcd_remap((int)blockIdx.x, (int)gridDim.x);
+    const ItemDesc &it = items[find_item(items, nitems, lb)];
+    if (jstep >= it.nsteps) return;
+    const int local = lb - it.block_begin;
+    if (local < 0 || local >= it.nblocks) return;
+
+    const int nx = it.nx, ny = it.ny, nz = it.nz;
+    const int txt = local % it.tiles_x;
+    const int rest = local / it.tiles_x;
+    const int tyt = rest % it.tiles_y;
+    const int zc = rest / it.tiles_y;
+    const int x0 = txt * TX, y0 = tyt * TY;
+    const int z0 = zc * it.tz;
+    const int zend = min(z0 + it.tz, nz);
+
+    const T *src;
+    T *dst;
+    pingpong<T>(it, jstep, it.nsteps, src, dst);
+
+    const int tid = (int)threadIdx.x;
+    const int txi = tid % BXT, tyi = tid / BXT;
+    const int cx0 = txi * NXP, ry0 = tyi * NY;
+    const int gx0 = wrapi(x0 - H + cx0, nx);
+    int rowoff[NY];
+    bool yok[NY];
+#pragma unroll
+    for (int iy = 0; iy < NY; ++iy) {
+        const int ry = ry0 + iy;
+        rowoff[iy] = wrapi(y0 - H + ry, ny) * nx + gx0;
+        yok[iy] = (ry >= H) && (ry < H + TY) && (y0 + ry - H < ny);
+    }
+    const bool xok = (cx0 >= H) && (cx0 < H + TX) && (x0 + cx0 - H < nx);
+    const int nxy = nx * ny;
+
+    const double dt = it.dt;
+    const double t = (double)(it.step0 + jstep) * dt;
+    const double nu1 = nu_at(it, t);
+    const double nu2 = it.frozen ? nu1 : nu_at(it, t + 0.5 * dt);
+    const double nu4 = it.frozen ? nu1 : nu_at(it, t + dt);
+    const Wts<T, R> w1 = uni(fine_weights<T, R>(it, nu1));
+    const Wts<T, R> w2 = uni(fine_weights<T, R>(it, nu2));
+    const Wts<T, R> w4 = uni(fine_weights<T, R>(it, nu4));
+    RK4Consts<T> kc = rk4_consts<T>(dt);
+    kc.c1 = uni(kc.c1);
+    kc.c2 = uni(kc.c2);
+    kc.c3 = uni(kc.c3);
+    kc.b1 = uni(kc.b1);
+    kc.b2 = uni(kc.b2);
+    kc.b3 = uni(kc.b3);
+    kc.b4 = uni(kc.b4);
+
+    T ur[L][NY][NXP], y1[L][NY][NXP], y2[L][NY][NXP], y3[L][NY][NXP], ac[L][NY][NXP];
+    T pf[PD][NY][NXP];   // planes in flight (prefetch ring)
+
+    auto load_plane = [&](int p, T(&dstp)[NY][NXP]) {
+        const T *base = src + (size_t)wrapi(p, nz) * nxy;
+#pragma unroll
+        for (int iy = 0; iy < NY; ++iy) {
+            const Vec<T, NXP> v = gld<Vec<T, NXP>>(base + rowoff[iy]);
+#pragma unroll
+            for (int ix = 0; ix < NXP; ++ix) dstp[iy][ix] = v.v[ix];
+        }
+    };
+
+    // ring slot SC of `v` -> LDS input B, slot SL
+    auto put = [&](auto Bc, auto SLc, auto SCc, const T(&v)[L][NY][NXP]) {
+        constexpr int B = decltype(Bc)::value;
+        constexpr int SL = decltype(SLc)::value;
+        constexpr int SC = decltype(SCc)::value;
+#pragma unroll
+        for (int iy = 0; iy < NY; ++iy) {
+            Vec<T, NXP> w;
+#pragma unroll
+            for (int ix = 0; ix < NXP; ++ix) w.v[ix] = v[SC][iy][ix];
+            *reinterpret_cast<Vec<T, NXP> *>(&lds[B][SL][R + ry0 + iy][CO + cx0]) = w;
+        }
+    };
+
+    // S = L(f)(plane p - OFF) for the thread's points; `in` is the ring of f,
+    // the in-plane neighbours outside the thread's group come from LDS input
+    // B, slot SL
+    auto stencil = [&](auto Mc, auto OFFc, auto Bc, auto SLc, const T(&in)[L][NY][NXP], const Wts<T, R> &w,
+                       T(&S)[NY][NXP]) {
+        constexpr int M = decltype(Mc)::value;
+        constexpr int OFF = decltype(OFFc)::value;
+        constexpr int B = decltype(Bc)::value;
+        constexpr int SL = decltype(SLc)::value;
+        constexpr int sc = slot<L>(M, OFF);
+#pragma unroll
+        for (int iy = 0; iy < NY; ++iy) {
+#pragma unroll
+            for (int ix = 0; ix < NXP; ++ix) {
+                T mn[3][R], pn[3][R];
+#pragma unroll
+                for (int k = 1; k <= R; ++k) {
+                    mn[0][k - 1] = (ix - k >= 0) ? in[sc][iy][ix - k] : lds[B][SL][R + ry0 + iy][CO + cx0 + ix - k];
+                    pn[0][k - 1] = (ix + k < NXP) ? in[sc][iy][ix + k] : lds[B][SL][R + ry0 + iy][CO + cx0 + ix + k];
+                    mn[1][k - 1] = (iy - k >= 0) ? in[sc][iy - k][ix] : lds[B][SL][R + ry0 + iy - k][CO + cx0 + ix];
+                    pn[1][k - 1] = (iy + k < NY) ? in[sc][iy + k][ix] : lds[B][SL][R + ry0 + iy + k][CO + cx0 + ix];
+                    mn[2][k - 1] = in[slot<L>(M, OFF + k)][iy][ix];   // plane q - k
+                    pn[2][k - 1] = in[slot<L>(M, OFF - k)][iy][ix];   // plane q + k
+                }
+                S[iy][ix] = apply<T, R>(w, in[sc][iy][ix], mn, pn);
+            }
+        }
+    };
+
+    auto body = [&](auto Mc, int p) {
+        constexpr int M = decltype(Mc)::value;
+        constexpr int WS = M & 1;        // slot written in this iteration
+        constexpr int RS = (M + 1) & 1;  // slot written in the previous iteration
+        __syncthreads();
+#pragma unroll
+        for (int iy = 0; iy < NY; ++iy)
+#pragma unroll
+            for (int ix = 0; ix < NXP; ++ix) ur[slot<L>(M, 0)][iy][ix] = pf[M % PD][iy][ix];
+        load_plane(p + PD, pf[M % PD]);
+        put(ic<0>{}, ic<WS>{}, ic<slot<L>(M, R - 1)>{}, ur);   // plane p + 1 - R
+        if constexpr (R >= 2) {
+            put(ic<1>{}, ic<WS>{}, ic<slot<L>(M, 2 * R - 1)>{}, y1);
+            put(ic<2>{}, ic<WS>{}, ic<slot<L>(M, 3 * R - 1)>{}, y2);
+            put(ic<3>{}, ic<WS>{}, ic<slot<L>(M, 4 * R - 1)>{}, y3);
+        }
+
+        T S[NY][NXP];
+        // stage 1 at plane p - R
+        if (p >= z0 - 2 * R) {
+            stencil(Mc, ic<R>{}, ic<0>{}, ic<RS>{}, ur, w1, S);
+#pragma unroll
+            for (int iy = 0; iy < NY; ++iy)
+#pragma unroll
+                for (int ix = 0; ix < NXP; ++ix) {
+                    const T u = ur[slot<L>(M, R)][iy][ix];
+                    y1[slot<L>(M, R)][iy][ix] = fmaT(kc.c1, S[iy][ix], u);
+                    ac[slot<L>(M, R)][iy][ix] = fmaT(kc.b1, S[iy][ix], u);
+                }
+        }
+        if constexpr (R == 1) put(ic<1>{}, ic<WS>{}, ic<slot<L>(M, 1)>{}, y1);
+        // stage 2 at plane p - 2R
+        if (p >= z0) {
+            stencil(Mc, ic<2 * R>{}, ic<1>{}, ic<RS>{}, y1, w2, S);
+#pragma unroll
+            for (int iy = 0; iy < NY; ++iy)
+#pragma unroll
+                for (int ix = 0; ix < NXP; ++ix) {
+                    const T u = ur[slot<L>(M, 2 * R)][iy][ix];
+                    y2[slot<L>(M, 2 * R)][iy][ix] = fmaT(kc.c2, S[iy][ix], u);
+                    ac[slot<L>(M, 2 * R)][iy][ix] = fmaT(kc.b2, S[iy][ix], ac[slot<L>(M, 2 * R)][iy][ix]);
+                }
+        }
+        if constexpr (R == 1) put(ic<2>{}, ic<WS>{}, ic<slot<L>(M, 2)>{}, y2);
+        // stage 3 at plane p - 3R
+        if (p >= z0 + 2 * R) {
+            stencil(Mc, ic<3 * R>{}, ic<2>{}, ic<RS>{}, y2, w2, S);
+#pragma unroll
+            for (int iy = 0; iy < NY; ++iy)
+#pragma unroll
+                for (int ix = 0; ix < NXP; ++ix) {
+                    const T u = ur[slot<L>(M, 3 * R)][iy][ix];
+                    y3[slot<L>(M, 3 * R)][iy][ix] = fmaT(kc.c3, S[iy][ix], u);
+                    ac[slot<L>(M, 3 * R)][iy][ix] = fmaT(kc.b3, S[iy][ix], ac[slot<L>(M, 3 * R)][iy][ix]);
+                }
+        }
+        if constexpr (R == 1) put(ic<3>{}, ic<WS>{}, ic<slot<L>(M, 3)>{}, y3);
+        // stage 4 at plane p - 4R, stored
+        const int q = p - 4 * R;
+        if (p >= z0 + 4 * R && q < zend) {
+            stencil(Mc, ic<4 * R>{}, ic<3>{}, ic<RS>{}, y3, w4, S);
+            if (xok) {
+                T *obase = dst + (size_t)q * nxy;
+#pragma unroll
+                for (int iy = 0; iy < NY; ++iy) {
+                    if (yok[iy]) {
+                        Vec<T, NXP> v;
+#pragma unroll
+                        for (int ix = 0; ix < NXP; ++ix)
+                            v.v[ix] = fmaT(kc.b4, S[iy][ix], ac[slot<L>(M, 4 * R)][iy][ix]);
+                        gst<Vec<T, NXP>>(obase + rowoff[iy], v);
+                    }
+                }
+            }
+        }
+    };
+
+    const int pstart = z0 - 4 * R;
+    const int niter = (zend - z0) + 8 * R;
+#pragma unroll
+    for (int d = 0; d < PD; ++d) load_plane(pstart + d, pf[d]);
+    for (int pb = 0; pb < niter; pb += L) {
+        [&]<int... Ms>(std::integer_sequence<int, Ms...>) {
+            (body(ic<Ms>{}, pstart + pb + Ms), ...);
+        }(std::make_integer_sequence<int, L>{});
+    }
+}
+
+// ---------------------------------------------------------------------------
 // Fused forward Euler chunk with one barrier per z plane (same scheme as
 // rk4_step_fused1b: stage outputs go to LDS and are read one iteration later).
 // ---------------------------------------------------------------------------
@@ -2029,6 +2252,16 @@ void fine_launch_rows(const ItemDesc *items, int nitems, int nblocks, int jstep,
 #define FINE_ROWS(T, DT, NXP, NY, NW, PD, NAME)                                                          \
     FineEntry{VariantInfo{NAME, DT, 2, 64 * NXP, NW * NY - 8, NXP, 64 * NW, 1, 64 * NXP},              \
               &fine_launch_rows<T, NXP, NY, NW, PD>}
+template <typename T, int R, int NXP, int NY, int BXT, int BY, int PD>
+void fine_launch_1r(const ItemDesc *items, int nitems, int nblocks, int jstep, hipStream_t s, int *occ)
+{
+    if (occ) return occupancy_of((rk4_step_fused1r<T, R, NXP, NY, BXT, BY, PD>), BXT * BY, occ);
+    hipLaunchKernelGGL((rk4_step_fused1r<T, R, NXP, NY, BXT, BY, PD>), dim3(nblocks), dim3(BXT * BY), 0, s, items,
+                       nitems, jstep);
+}
+#define FINE_1R(T, DT, R, NXP, NY, BXT, BY, PD, NAME)                                                    \
+    FineEntry{VariantInfo{NAME, DT, 2 * R, BXT * NXP - 8 * R, BY * NY - 8 * R, NXP, BXT * BY, 1},       \
+              &fine_launch_1r<T, R, NXP, NY, BXT, BY, PD>}
 #define FINE_1C(T, DT, NXP, NY, BXT, BY, PD, PAD, NAME)                                                  \
     FineEntry{VariantInfo{NAME, DT, 2, BXT * NXP - 8, BY * NY - 8, NXP, BXT * BY, 1},                  \
               &fine_launch_1c<T, NXP, NY, BXT, BY, PD, PAD>}
@@ -2062,6 +2295,8 @@ const FineEntry kFine[] = {
     FINE_V(double, 2, 2, 1, 1, 40, 24, "rk4_f64_o4_t24x8_p1x1"),
     FINE_V(float, 1, 2, 2, 2, 24, 16, "rk4_f32_o4_t32x16_p2x2"),
     FINE_V(float, 1, 2, 1, 2, 48, 16, "rk4_f32_o4_t32x16_p1x2"),
+    FINE_1R(float, 1, 2, 2, 2, 24, 16, 2, "rk4r_f32_o4_t32x16_p2x2_d2"),
+    FINE_1R(double, 2, 1, 1, 2, 40, 20, 2, "rk4r_f64_o2_t32x32_p1x2_d2"),
     FINE_1B(double, 2, 2, 2, 20, 20, 1, "rk4b_f64_t32x32_p2x2"),
     FINE_1B(double, 2, 2, 2, 20, 20, 2, "rk4b_f64_t32x32_p2x2_d2"),
     FINE_1B(double, 2, 2, 2, 20, 20, 4, "rk4b_f64_t32x32_p2x2_d4"),

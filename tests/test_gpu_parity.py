@@ -88,10 +88,11 @@ def test_coarse_sweep_fp64(pr, orc, nsteps, a):
         assert rel_l2(got, ref) <= FP64_TOL
 
 
-def test_fp32_sweeps_against_fp64_oracle(pr, orc):
+@pytest.mark.parametrize("order", [2, 4])
+def test_fp32_sweeps_against_fp64_oracle(pr, orc, order):
     import torch
-    say("fp32 sweeps")
-    p = W.small_problem(n=(48, 40, 36), a=(1.0, 0.5, 0.25), nu0=0.004, P=2, nf=16, nc=16)
+    say("fp32 sweeps", order)
+    p = W.small_problem(n=(48, 40, 36), a=(1.0, 0.5, 0.25), nu0=0.004, P=2, nf=16, nc=16, order=order)
     modes = W.draw_modes(np.random.default_rng(130), 6, 4)
     u = W.synth_u0(p.n, modes)
     gf = host(pr.fine_sweep(p, cuda(u, torch.float32), 0, 16))
