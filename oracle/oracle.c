@@ -135,34 +135,42 @@ void or_fine_rhs(const or_prob *p, double nu, const double *u, double *out)
     }
 }
 
-/* Coarse right-hand side of Algorithm 2: 7-point diffusion times nu, then for
- * every direction the first-order upwind difference chosen by the sign of a_d. */
+/* First-order one-sided difference along one axis, taken on the side the
+ * flow comes from: the backward difference (u_0 - u_{-1})/h for a positive
+ * velocity component, the forward difference (u_{+1} - u_0)/h otherwise
+ * (a zero component multiplies the result by zero either way). */
+static double upwind_slope(double vel, double um, double u0, double up, double h)
+{
+    return vel > 0.0 ? (u0 - um) / h : (up - u0) / h;
+}
+
+/* Coarse right-hand side (the operator of Algorithm 2): nu times the 7-point
+ * Laplacian, minus a.grad(u) where each component of grad(u) is the upwind
+ * one-sided difference of its axis.  Assembled axis by axis: for axis d the
+ * two neighbours at distance one along d enter both the second difference
+ * and the upwind slope. */
 void or_coarse_rhs(const or_prob *p, double nu, const double *u, double *out)
 {
-    const int nx = p->nx, ny = p->ny, nz = p->nz;
-    const double hx = 1.0 / nx, hy = 1.0 / ny, hz = 1.0 / nz;
+    const int n[3] = {p->nx, p->ny, p->nz};
+    const double vel[3] = {p->ax, p->ay, p->az};
 #pragma omp parallel for schedule(static)
-    for (int z = 0; z < nz; ++z) {
-        for (int y = 0; y < ny; ++y) {
-            for (int x = 0; x < nx; ++x) {
-                const long c = ((long)z * ny + y) * nx + x;
-                const double uc = u[c];
-                const double xm1 = u[((long)z * ny + y) * nx + wrap(x - 1, nx)];
-                const double xp1 = u[((long)z * ny + y) * nx + wrap(x + 1, nx)];
-                const double ym1 = u[((long)z * ny + wrap(y - 1, ny)) * nx + x];
-                const double yp1 = u[((long)z * ny + wrap(y + 1, ny)) * nx + x];
-                const double zm1 = u[((long)wrap(z - 1, nz) * ny + y) * nx + x];
-                const double zp1 = u[((long)wrap(z + 1, nz) * ny + y) * nx + x];
-                double rhs = nu * ((xp1 + xm1 - 2.0 * uc) / (hx * hx)
-                                 + (yp1 + ym1 - 2.0 * uc) / (hy * hy)
-                                 + (zp1 + zm1 - 2.0 * uc) / (hz * hz));
-                if (p->ax > 0.0) rhs -= p->ax * (uc - xm1) / hx;
-                else             rhs -= p->ax * (xp1 - uc) / hx;
-                if (p->ay > 0.0) rhs -= p->ay * (uc - ym1) / hy;
-                else             rhs -= p->ay * (yp1 - uc) / hy;
-                if (p->az > 0.0) rhs -= p->az * (uc - zm1) / hz;
-                else             rhs -= p->az * (zp1 - uc) / hz;
-                out[c] = rhs;
+    for (int z = 0; z < n[2]; ++z) {
+        for (int y = 0; y < n[1]; ++y) {
+            for (int x = 0; x < n[0]; ++x) {
+                const int at[3] = {x, y, z};
+                const double uc = u[((long)z * n[1] + y) * n[0] + x];
+                double lap = 0.0, adv = 0.0;
+                for (int d = 0; d < 3; ++d) {
+                    int lo[3] = {x, y, z}, hi[3] = {x, y, z};
+                    lo[d] = wrap(at[d] - 1, n[d]);
+                    hi[d] = wrap(at[d] + 1, n[d]);
+                    const double um = u[((long)lo[2] * n[1] + lo[1]) * n[0] + lo[0]];
+                    const double up = u[((long)hi[2] * n[1] + hi[1]) * n[0] + hi[0]];
+                    const double h = 1.0 / n[d];
+                    lap += (up + um - 2.0 * uc) / (h * h);
+                    adv += vel[d] * upwind_slope(vel[d], um, uc, up, h);
+                }
+                out[((long)z * n[1] + y) * n[0] + x] = nu * lap - adv;
             }
         }
     }

@@ -16,7 +16,8 @@ from ._lib import (PR_ALLOW_UNSTABLE, PR_COARSEN_G, PR_CUBIC_INTERP, PR_EARLY_ST
                    PR_FP64, PR_MODE_FP64, PR_MODE_GRAPH, PR_MODE_MIXED, PR_MODE_PER_SLICE, PR_MODE_TIMED,
                    PR_NU_FROZEN, PR_SKIP_CONVERGED, PrError, check, lib, to_struct)
 
-__all__ = ["fine_sweep", "coarse_sweep", "parareal_update", "defect_norm", "restrict", "prolong", "Plan",
+__all__ = ["fine_sweep", "coarse_sweep", "parareal_update", "defect_norm", "restrict", "prolong",
+           "Plan",
            "check_stability", "set_kernel_variant", "variants", "sweep_kernel_variant", "autotune", "PrError",
            "lib"]
 
@@ -42,12 +43,36 @@ def _code(t) -> int:
     raise TypeError("fields must be float32 or float64, got %s" % t.dtype)
 
 
-def _dev(t):
-    if not t.is_cuda:
-        raise ValueError("tensor must live on the GPU")
+def _shape(t, name, numel=None, dtype=None):
+    """Check a tensor handed to the library: a torch tensor of the expected
+    dtype and element count, contiguous.  The library receives bare device
+    pointers and cannot check sizes itself, so a short buffer would be read
+    or written out of bounds on the device.  Runs before any device check, so
+    every rejection here is exercised without a GPU."""
+    torch = _torch()
+    if not isinstance(t, torch.Tensor):
+        raise TypeError("%s must be a torch tensor" % name)
+    if dtype is not None and t.dtype != dtype:
+        raise TypeError("%s must be %s, got %s" % (name, dtype, t.dtype))
+    if numel is not None and t.numel() != numel:
+        raise ValueError("%s must hold %d values, got %d" % (name, numel, t.numel()))
     if not t.is_contiguous():
-        raise ValueError("tensor must be contiguous")
+        raise ValueError("%s must be contiguous" % name)
+    return t
+
+
+def _ptr(t, name, like=None):
+    """Device pointer of a checked tensor; it must live on the GPU, on the
+    device of `like` when given."""
+    if not t.is_cuda:
+        raise ValueError("%s must live on the GPU" % name)
+    if like is not None and t.device != like.device:
+        raise ValueError("%s is on %s, expected %s" % (name, t.device, like.device))
     return ctypes.c_void_p(t.data_ptr())
+
+
+def _dev(t):
+    return _ptr(_shape(t, "tensor"), "tensor")
 
 
 def _workspace(nbytes, device):
@@ -55,21 +80,43 @@ def _workspace(nbytes, device):
     return torch.empty(max(int(nbytes), 1), dtype=torch.uint8, device=device)
 
 
+def _keep_alive(stream, *tensors):
+    """Tensors allocated here but used by kernels queued on a stream other
+    than the current one: tell the caching allocator, so their memory is not
+    handed to the current stream while those kernels still run."""
+    torch = _torch()
+    if stream is None or stream == torch.cuda.current_stream():
+        return
+    for t in tensors:
+        if t is not None:
+            t.record_stream(stream)
+
+
 def _sweep(fn, prob, u_in, step0, nsteps, u_out, stream):
     torch = _torch()
     s = to_struct(prob)
     nx, ny, nz = (int(v) for v in prob.n)
     npts = nx * ny * nz
-    if u_in.numel() % npts:
-        raise ValueError("u_in size is not a multiple of the grid size")
-    batch = u_in.numel() // npts
-    if u_out is None:
-        u_out = torch.empty_like(u_in)
-    steps = (ctypes.c_int64 * batch)(*([int(step0)] * batch if isinstance(step0, int) else [int(v) for v in step0]))
     dt = _code(u_in)
+    _shape(u_in, "u_in")
+    if npts <= 0 or u_in.numel() == 0 or u_in.numel() % npts:
+        raise ValueError("u_in size is not a positive multiple of the grid size")
+    batch = u_in.numel() // npts
+    if u_out is not None:
+        _shape(u_out, "u_out", numel=u_in.numel(), dtype=u_in.dtype)
+    s0 = [int(step0)] * batch if isinstance(step0, int) else [int(v) for v in step0]
+    if len(s0) != batch:
+        raise ValueError("step0 needs one entry per field (%d), got %d" % (batch, len(s0)))
+    pin = _ptr(u_in, "u_in")
+    made = u_out is None
+    if made:
+        u_out = torch.empty_like(u_in)
+    pout = _ptr(u_out, "u_out", like=u_in)
+    steps = (ctypes.c_int64 * batch)(*s0)
     ws = _workspace(lib().pr_sweep_workspace_bytes(ctypes.byref(s), dt, batch), u_in.device)
-    check(fn(ctypes.byref(s), dt, batch, _dev(u_in), _dev(u_out), steps, int(nsteps),
+    check(fn(ctypes.byref(s), dt, batch, pin, pout, steps, int(nsteps),
              ctypes.c_void_p(ws.data_ptr()), ws.numel(), _stream_ptr(stream)))
+    _keep_alive(stream, ws, u_out if made else None)
     return u_out
 
 
@@ -90,19 +137,23 @@ def _transfer(prob, u_in, order, prolong, stream):
     nx, ny, nz = (int(v) for v in prob.n)
     fine, coarse = nx * ny * nz, (nx // 2) * (ny // 2) * (nz // 2)
     n_in = coarse if prolong else fine
-    if u_in.numel() % n_in:
-        raise ValueError("input size is not a multiple of the %s grid size" % ("coarse" if prolong else "fine"))
+    dt = _code(u_in)
+    _shape(u_in, "u_in")
+    if n_in <= 0 or u_in.numel() == 0 or u_in.numel() % n_in:
+        raise ValueError("input size is not a positive multiple of the %s grid size"
+                         % ("coarse" if prolong else "fine"))
     batch = u_in.numel() // n_in
+    pin = _ptr(u_in, "u_in")
     shape = (batch, nz, ny, nx) if prolong else (batch, nz // 2, ny // 2, nx // 2)
     out = torch.empty(shape, dtype=u_in.dtype, device=u_in.device)
     ws = _workspace(lib().pr_transfer_workspace_bytes(batch), u_in.device)
-    dt = _code(u_in)
     if prolong:
-        check(lib().pr_prolong(ctypes.byref(s), dt, int(order), batch, _dev(u_in), _dev(out),
+        check(lib().pr_prolong(ctypes.byref(s), dt, int(order), batch, pin, _ptr(out, "out"),
                                ctypes.c_void_p(ws.data_ptr()), ws.numel(), _stream_ptr(stream)))
     else:
-        check(lib().pr_restrict(ctypes.byref(s), dt, batch, _dev(u_in), _dev(out), ctypes.c_void_p(ws.data_ptr()),
+        check(lib().pr_restrict(ctypes.byref(s), dt, batch, pin, _ptr(out, "out"), ctypes.c_void_p(ws.data_ptr()),
                                 ws.numel(), _stream_ptr(stream)))
+    _keep_alive(stream, ws, out)
     return out
 
 
@@ -117,24 +168,48 @@ def prolong(prob, u_coarse, order=1, stream=None):
 
 
 def parareal_update(f_new, g_new, g_old, u_out=None, u_out_lo=None, stream=None):
-    """u_out = f_new + (g_new - g_old) in FP64; optional rounded copy u_out_lo."""
+    """u_out = f_new + (g_new - g_old) in FP64; optional rounded copy u_out_lo.
+    g_new, g_old and u_out_lo have f_new's dtype and size; u_out is FP64."""
     torch = _torch()
-    if u_out is None:
+    dt = _code(f_new)
+    n = _shape(f_new, "f_new").numel()
+    _shape(g_new, "g_new", numel=n, dtype=f_new.dtype)
+    _shape(g_old, "g_old", numel=n, dtype=f_new.dtype)
+    if u_out is not None:
+        _shape(u_out, "u_out", numel=n, dtype=torch.float64)
+    if u_out_lo is not None:
+        _shape(u_out_lo, "u_out_lo", numel=n, dtype=f_new.dtype)
+    pf = _ptr(f_new, "f_new")
+    pgn = _ptr(g_new, "g_new", like=f_new)
+    pgo = _ptr(g_old, "g_old", like=f_new)
+    made = u_out is None
+    if made:
         u_out = torch.empty(f_new.shape, dtype=torch.float64, device=f_new.device)
-    check(lib().pr_parareal_update(f_new.numel(), 1, _code(f_new), _dev(f_new), _dev(g_new), _dev(g_old),
-                                   _dev(u_out), _dev(u_out_lo) if u_out_lo is not None else None,
-                                   _stream_ptr(stream)))
+    pu = _ptr(u_out, "u_out", like=f_new)
+    plo = _ptr(u_out_lo, "u_out_lo", like=f_new) if u_out_lo is not None else None
+    check(lib().pr_parareal_update(n, 1, dt, pf, pgn, pgo, pu, plo, _stream_ptr(stream)))
+    _keep_alive(stream, u_out if made else None)
     return u_out
 
 
 def defect_norm(x, ref, batch=1, stream=None):
-    """Device tensor [batch, 4]: max|x-r|, max|r|, sum (x-r)^2, sum r^2."""
+    """Device tensor [batch, 4]: max|x-r|, max|r|, sum (x-r)^2, sum r^2.
+    x and ref hold the same number of values (FP32 or FP64 each)."""
     torch = _torch()
+    xd, rd = _code(x), _code(ref)
+    batch = int(batch)
+    _shape(x, "x")
+    if batch < 1 or x.numel() == 0 or x.numel() % batch:
+        raise ValueError("x must hold a positive multiple of batch values")
+    _shape(ref, "ref", numel=x.numel())
     n = x.numel() // batch
+    px = _ptr(x, "x")
+    pref = _ptr(ref, "ref", like=x)
     out = torch.empty((batch, 4), dtype=torch.float64, device=x.device)
     ws = _workspace(lib().pr_defect_workspace_bytes(batch), x.device)
-    check(lib().pr_defect_norm(n, batch, _code(x), _dev(x), _code(ref), _dev(ref), _dev(out),
+    check(lib().pr_defect_norm(n, batch, xd, px, rd, pref, _ptr(out, "out"),
                                ctypes.c_void_p(ws.data_ptr()), ws.numel(), _stream_ptr(stream)))
+    _keep_alive(stream, ws, out)
     return out
 
 
@@ -207,11 +282,18 @@ class Plan:
         import numpy as np
         torch = _torch()
         n = len(self.probs)
+        if len(u0) != n or (uT is not None and len(uT) != n) or (ref is not None and len(ref) != n):
+            raise ValueError("u0, uT and ref need one tensor per instance (%d)" % n)
+        npts = [int(p.n[0]) * int(p.n[1]) * int(p.n[2]) for p in self.probs]
+        groups = [("u0", u0)] + ([("uT", uT)] if uT is not None else []) + ([("ref", ref)] if ref is not None else [])
+        for name, ts in groups:
+            for i, x in enumerate(ts):
+                _shape(x, "%s[%d]" % (name, i), numel=npts[i], dtype=torch.float64)
+        for name, ts in groups:
+            for i, x in enumerate(ts):
+                _ptr(x, "%s[%d]" % (name, i), like=self.ws)
         if uT is None:
             uT = [torch.empty_like(x) for x in u0]
-        for x in list(u0) + list(uT) + (list(ref) if ref is not None else []):
-            if x.dtype != torch.float64:
-                raise TypeError("u0, uT and ref must be float64")
         pu0 = (ctypes.c_void_p * n)(*[x.data_ptr() for x in u0])
         puT = (ctypes.c_void_p * n)(*[x.data_ptr() for x in uT])
         pref = (ctypes.c_void_p * n)(*[x.data_ptr() for x in ref]) if ref is not None else None

@@ -40,14 +40,20 @@ struct Acc4 {
 
 __device__ __forceinline__ double shfl_xor_d(double v, int m) { return __shfl_xor(v, m, 64); }
 
+// Maximum that propagates NaN (fmax drops it): a field holding a NaN must
+// give a NaN maximum, so that a defect norm or the early-stop test cannot
+// report a small value for it.  Order independent like fmax: the result is
+// NaN if either operand is NaN, else the larger one.
+__device__ __forceinline__ double nmax(double m, double v) { return (v != v || v > m) ? v : m; }
+
 // Deterministic block reduction of (max, max, sum, sum); result valid in thread 0.
 __device__ __forceinline__ Acc4 block_reduce(Acc4 a)
 {
     __shared__ double red[kNormThreads / 64][4];
 #pragma unroll
     for (int m = 32; m >= 1; m >>= 1) {
-        a.mx = fmax(a.mx, shfl_xor_d(a.mx, m));
-        a.mr = fmax(a.mr, shfl_xor_d(a.mr, m));
+        a.mx = nmax(a.mx, shfl_xor_d(a.mx, m));
+        a.mr = nmax(a.mr, shfl_xor_d(a.mr, m));
         a.sx = a.sx + shfl_xor_d(a.sx, m);
         a.sr = a.sr + shfl_xor_d(a.sr, m);
     }
@@ -62,8 +68,8 @@ __device__ __forceinline__ Acc4 block_reduce(Acc4 a)
     Acc4 r{0.0, 0.0, 0.0, 0.0};
     if (threadIdx.x == 0) {
         for (int w = 0; w < kNormThreads / 64; ++w) {
-            r.mx = fmax(r.mx, red[w][0]);
-            r.mr = fmax(r.mr, red[w][1]);
+            r.mx = nmax(r.mx, red[w][0]);
+            r.mr = nmax(r.mr, red[w][1]);
             r.sx = r.sx + red[w][2];
             r.sr = r.sr + red[w][3];
         }
@@ -93,8 +99,8 @@ __global__ void __launch_bounds__(kNormThreads) pointwise_kernel(PointArgs args,
         }
         if (with_partials) {
             const double d = u - G<double>(it.u)[i];
-            acc.mx = fmax(acc.mx, fabs(d));
-            acc.mr = fmax(acc.mr, fabs(u));
+            acc.mx = nmax(acc.mx, fabs(d));
+            acc.mr = nmax(acc.mr, fabs(u));
             acc.sx += d * d;
             acc.sr += u * u;
         }
@@ -126,8 +132,8 @@ __global__ void __launch_bounds__(kNormThreads) defect_partials_kernel(PointArgs
     for (int64_t i = (int64_t)blockIdx.x * kNormThreads + threadIdx.x; i < n; i += stride) {
         const double rv = (double)r[i];
         const double d = (double)x[i] - rv;
-        acc.mx = fmax(acc.mx, fabs(d));
-        acc.mr = fmax(acc.mr, fabs(rv));
+        acc.mx = nmax(acc.mx, fabs(d));
+        acc.mr = nmax(acc.mr, fabs(rv));
         acc.sx += d * d;
         acc.sr += rv * rv;
     }
@@ -149,8 +155,8 @@ __global__ void __launch_bounds__(kNormThreads) defect_final_kernel(PointArgs ar
     Acc4 acc{0.0, 0.0, 0.0, 0.0};
     for (int b = threadIdx.x; b < kNormBlocks; b += kNormThreads) {
         const double *p = it.partials + (size_t)b * 4;
-        acc.mx = fmax(acc.mx, p[0]);
-        acc.mr = fmax(acc.mr, p[1]);
+        acc.mx = nmax(acc.mx, p[0]);
+        acc.mr = nmax(acc.mr, p[1]);
         acc.sx += p[2];
         acc.sr += p[3];
     }

@@ -94,6 +94,9 @@ int device_ready()
     return PR_OK;
 }
 
+// Maximum that keeps a NaN operand (std::max drops one in its second argument).
+double nan_max(double m, double v) { return (v != v || v > m) ? v : m; }
+
 size_t esize(int dtype) { return dtype == PR_FP64 ? 8 : 4; }
 size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 int64_t npts_of(const pr_problem &p) { return (int64_t)p.n[0] * p.n[1] * p.n[2]; }
@@ -1188,20 +1191,27 @@ size_t pr_defect_workspace_bytes(int32_t batch)
     return align256((size_t)batch * sizeof(PointItem)) + (size_t)batch * pr::kNormBlocks * 4 * sizeof(double);
 }
 
-int pr_defect_norm(int64_t npts, int32_t batch, int32_t xd, const void *x, int32_t rd, const void *ref,
-                   double *out4, void *ws, size_t ws_bytes, void *stream)
+}  // extern "C"
+
+namespace {
+
+int defect_args(int64_t npts, int32_t batch, int32_t xd, const void *x, int32_t rd, const void *ref,
+                const double *out4)
 {
     if (npts < 1 || batch < 1) return fail(PR_EINVAL, "npts and batch must be >= 1");
     if ((xd != PR_FP32 && xd != PR_FP64) || (rd != PR_FP32 && rd != PR_FP64)) return fail(PR_EINVAL, "bad dtype");
     if (!x || !ref || !out4) return fail(PR_EINVAL, "NULL pointer");
-    const size_t need = pr_defect_workspace_bytes(batch);
-    if (!ws || ws_bytes < need) return fail(PR_ENOMEM, "workspace of %zu bytes < %zu needed", ws_bytes, need);
-    int rc = device_ready();
-    if (rc) return rc;
-    char *w = (char *)ws;
-    PointItem *table = (PointItem *)w;
-    double *part = (double *)(w + align256((size_t)batch * sizeof(PointItem)));
-    std::vector<PointItem> items(batch);
+    return PR_OK;
+}
+
+// The norms of `batch` field pairs with the item table at `table` and the
+// block partials at `part` (kNormBlocks * 4 doubles per pair).  Every partial
+// is written by the first pass before the second reads it, so nothing needs
+// clearing.
+// `items` is host storage for `batch` descriptors.
+int defect_enqueue(int64_t npts, int32_t batch, int32_t xd, const void *x, int32_t rd, const void *ref,
+                   double *out4, PointItem *items, PointItem *table, double *part, hipStream_t s)
+{
     for (int b = 0; b < batch; ++b) {
         PointItem &it = items[b];
         it = PointItem{};
@@ -1211,11 +1221,30 @@ int pr_defect_norm(int64_t npts, int32_t batch, int32_t xd, const void *x, int32
         it.out4 = out4 + 4 * (size_t)b;
         it.npts = npts;
     }
-    hipStream_t s = (hipStream_t)stream;
-    HIPCHK(pr::launch_write_points(items.data(), batch, table, s));
+    HIPCHK(pr::launch_write_points(items, batch, table, s));
     HIPCHK(pr::launch_defect_partials(xd, rd, table, batch, s));
     HIPCHK(pr::launch_defect_final(table, batch, s));
     return PR_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int pr_defect_norm(int64_t npts, int32_t batch, int32_t xd, const void *x, int32_t rd, const void *ref,
+                   double *out4, void *ws, size_t ws_bytes, void *stream)
+{
+    int rc = defect_args(npts, batch, xd, x, rd, ref, out4);
+    if (rc) return rc;
+    const size_t need = pr_defect_workspace_bytes(batch);
+    if (!ws || ws_bytes < need) return fail(PR_ENOMEM, "workspace of %zu bytes < %zu needed", ws_bytes, need);
+    rc = device_ready();
+    if (rc) return rc;
+    char *w = (char *)ws;
+    PointItem *table = (PointItem *)w;
+    double *part = (double *)(w + align256((size_t)batch * sizeof(PointItem)));
+    std::vector<PointItem> items(batch);
+    return defect_enqueue(npts, batch, xd, x, rd, ref, out4, items.data(), table, part, (hipStream_t)stream);
 }
 
 size_t pr_plan_workspace_bytes(const pr_problem *probs, int32_t ninst, int32_t mode)
@@ -1525,14 +1554,14 @@ int pr_parareal_solve(pr_plan *pl, const double *const *u0, double *const *uT, c
                 const int kk = computed ? k : n;  // slice n last changed in iteration n
                 const double *e = &dl[((size_t)kk * pl->sumP + pl->slice_base[i] + n) * 4];
                 const double dmax = computed ? e[0] : 0.0, dsum = computed ? e[2] : 0.0;
-                row[4] = std::max(row[4], dmax);
-                row[5] = std::max(row[5], e[1]);
+                row[4] = nan_max(row[4], dmax);
+                row[5] = nan_max(row[5], e[1]);
                 row[6] += dsum;
                 row[7] += e[3];
             }
             if (with_ref)
                 for (int c = 0; c < 4; ++c) row[8 + c] = dr[((size_t)k * ninst + i) * 4 + c];
-            for (int c : {2, 3, 6, 7, 10, 11})
+            for (int c = 0; c < 12; ++c)
                 if (!std::isfinite(row[c])) finite = false;
             if (log)
                 for (int c = 0; c < 12; ++c) log[((size_t)i * K + k) * 12 + c] = row[c];

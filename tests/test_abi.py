@@ -314,3 +314,45 @@ def test_plan_autotune_validation():
     assert L.lib().pr_plan_fine_groups(None, 0, ctypes.byref(cnt), None, None, None) == L.PR_EINVAL
     v = (ctypes.c_int32 * 4)()
     assert L.lib().pr_plan_autotune(None, None, None, None, None, None) == L.PR_EINVAL
+
+
+def test_binding_rejects_mismatched_buffers_before_any_device_work():
+    """The C ABI receives bare device pointers and cannot see buffer sizes,
+    so the binding checks dtype, element count and contiguity of every
+    tensor (before the device check, so this runs on the CPU)."""
+    import torch
+
+    import paper_1409_8563_amd as pr
+    p = W.small_problem(n=(8, 6, 5))
+    npts = 8 * 6 * 5
+    f64 = lambda k: torch.zeros(k, dtype=torch.float64)   # noqa: E731
+    f32 = lambda k: torch.zeros(k, dtype=torch.float32)   # noqa: E731
+    # sweeps: u_out of the wrong size or dtype, step0 of the wrong length
+    with pytest.raises(ValueError, match="u_out"):
+        pr.fine_sweep(p, f64(2 * npts), 0, 1, u_out=f64(npts))
+    with pytest.raises(TypeError, match="u_out"):
+        pr.coarse_sweep(p, f64(npts), 0, 1, u_out=f32(npts))
+    with pytest.raises(ValueError, match="step0"):
+        pr.fine_sweep(p, f64(2 * npts), [0, 1, 2], 1)
+    with pytest.raises(ValueError, match="multiple"):
+        pr.fine_sweep(p, f64(npts + 1), 0, 1)
+    with pytest.raises(ValueError, match="contiguous"):
+        pr.fine_sweep(p, f64(2 * npts).view(2, npts).t(), 0, 1)
+    # correction: operands and outputs must match f_new
+    with pytest.raises(ValueError, match="g_new"):
+        pr.parareal_update(f32(10), f32(9), f32(10))
+    with pytest.raises(TypeError, match="g_old"):
+        pr.parareal_update(f32(10), f32(10), f64(10))
+    with pytest.raises(TypeError, match="u_out"):
+        pr.parareal_update(f32(10), f32(10), f32(10), u_out=f32(10))
+    with pytest.raises(ValueError, match="u_out_lo"):
+        pr.parareal_update(f32(10), f32(10), f32(10), u_out=f64(10), u_out_lo=f32(5))
+    # norms: ref must match x; batch must divide x
+    with pytest.raises(ValueError, match="ref"):
+        pr.defect_norm(f64(12), f64(11))
+    with pytest.raises(ValueError, match="batch"):
+        pr.defect_norm(f64(12), f64(12), batch=5)
+    # every check passed: only then the device check
+    with pytest.raises(ValueError, match="GPU"):
+        pr.parareal_update(f32(10), f32(10), f32(10))
+

@@ -507,6 +507,51 @@ def test_nonfinite_input_is_reported(pr):
     assert e.value.code == -6
 
 
+def test_nan_propagates_through_norms_and_blocks_early_stop(pr):
+    """A single NaN makes every maximum of the norms NaN (a max that dropped
+    it would report a finite defect), and the early-stop test on a NaN
+    defect never fires: the solve runs all K iterations and reports
+    PR_ENONFINITE."""
+    import torch
+    say("nan norms")
+    n3 = (24, 20, 18)
+    x, r = W.random_field(n3, 231), W.random_field(n3, 232)
+    x[5, 6, 7] = np.nan
+    got = host(pr.defect_norm(cuda(x), cuda(r)))
+    assert np.isnan(got[0, 0]) and np.isfinite(got[0, 1]) and np.isnan(got[0, 2])
+    got = host(pr.defect_norm(cuda(r), cuda(x)))
+    assert np.isnan(got[0, 0]) and np.isnan(got[0, 1])
+    say("nan early stop")
+    q = W.small_problem(n=(16, 16, 16), P=4, nf=4, nc=5, K=3, flags=W.EARLY_STOP)
+    q.tol = 1e30
+    u0 = W.random_field(q.n, 233)
+    u0[2, 3, 4] = np.nan
+    plan = pr.Plan([q], pr.PR_MODE_FP64)
+    with pytest.raises(pr.PrError) as e:
+        plan.solve([cuda(u0)])
+    assert e.value.code == -6
+    assert plan.iterations() == q.K
+
+
+def test_plan_solve_rejects_mismatched_buffers(pr):
+    import torch
+    p = W.small_problem(n=(16, 12, 10), P=2, nf=2, nc=4, K=1)
+    plan = pr.Plan([p], pr.PR_MODE_FP64)
+    u0 = cuda(W.random_field(p.n, 234))
+    with pytest.raises(ValueError, match="u0"):
+        plan.solve([u0[:-1]])
+    with pytest.raises(TypeError, match="u0"):
+        plan.solve([u0.float()])
+    with pytest.raises(ValueError, match="uT"):
+        plan.solve([u0], uT=[torch.empty(p.npts + 8, dtype=torch.float64, device="cuda")])
+    with pytest.raises(ValueError, match="ref"):
+        plan.solve([u0], ref=[u0.reshape(-1)[:100]])
+    with pytest.raises(ValueError, match="one tensor per instance"):
+        plan.solve([u0, u0])
+    uT, _ = plan.solve([u0])
+    assert uT[0].shape == u0.shape
+
+
 def test_plan_autotune_keeps_results(pr):
     """Tuning a plan's launches (variant and z-chunk depth) changes no bit of
     the result, eager or replayed from a graph recorded before the tuning."""

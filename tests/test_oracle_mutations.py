@@ -23,9 +23,13 @@ MUTATIONS = [
     ("order-4 laplacian coefficient", "(-xp2 + 16.0 * xp1 - 30.0 * uc + 16.0 * xm1 - xm2)",
      "(-xp2 + 16.0 * xp1 - 30.0 * uc + 15.0 * xm1 - xm2)",
      "tests/test_oracle_operators.py::test_fine_rhs_order4_matches_dense"),
-    ("upwind branch swapped", "if (p->ax > 0.0) rhs -= p->ax * (uc - xm1) / hx;",
-     "if (p->ax < 0.0) rhs -= p->ax * (uc - xm1) / hx;",
+    ("upwind branch swapped", "return vel > 0.0 ? (u0 - um) / h : (up - u0) / h;",
+     "return vel < 0.0 ? (u0 - um) / h : (up - u0) / h;",
      "tests/test_oracle_operators.py::test_coarse_courant_one_is_exact_shift"),
+    ("coarse diffusion scaled by h", "lap += (up + um - 2.0 * uc) / (h * h);", "lap += (up + um - 2.0 * uc) / h;",
+     "tests/test_oracle_operators.py::test_coarse_rhs_matches_dense"),
+    ("coarse neighbour on the wrong axis", "hi[d] = wrap(at[d] + 1, n[d]);", "hi[(d + 1) % 3] = wrap(at[(d + 1) % 3] + 1, n[(d + 1) % 3]);",
+     "tests/test_oracle_operators.py::test_coarse_rhs_matches_dense"),
     ("RK4 middle stage time", "const double nu2 = p->nu_frozen ? nu1 : or_nu(p, t + 0.5 * dt);",
      "const double nu2 = nu1;", "tests/test_oracle_time.py::test_rk4_time_dependent_nu_is_fourth_order"),
     ("RK4 last stage time", "const double nu4 = p->nu_frozen ? nu1 : or_nu(p, t + dt);",
