@@ -68,6 +68,39 @@ def cpu_baseline(p, u0_np, budget_s=15.0):
                                                                                         dt)}
 
 
+def copy_ceiling(pr, torch, nbytes):
+    """Achievable HBM bandwidth of a plain copy of `nbytes` with the library's
+    own streaming kernel (pr_copy_probe): best over its variants and grid
+    sizes, each the best of three windows of 10 copies timed with HIP events
+    on the current stream.  GB/s counts read + write bytes."""
+    a = torch.empty(nbytes // 8, dtype=torch.float64, device="cuda").normal_()
+    b = torch.empty_like(a)
+    best = (0.0, None)
+    for variant in (0, 1, 2, 3):
+        for bpc in (2, 4, 8, 16):
+            pr.copy_probe(a, b, variant, bpc)
+            torch.cuda.synchronize()
+            t = float("inf")
+            for _ in range(3):
+                e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                e0.record()
+                for _ in range(10):
+                    pr.copy_probe(a, b, variant, bpc)
+                e1.record()
+                torch.cuda.synchronize()
+                t = min(t, e0.elapsed_time(e1) / 10)
+            gbs = 2 * nbytes / (t * 1e-3) / 1e9
+            if gbs > best[0]:
+                best = (gbs, (variant, bpc, t))
+    ok = bool(torch.equal(a, b))
+    del a, b
+    torch.cuda.empty_cache()
+    gbs, (variant, bpc, t) = best
+    return {"gbs": round(gbs, 1), "frac_of_peak": round(gbs / HBM_PEAK_GBS, 4), "bytes_copied": nbytes,
+            "kernel": "copy_probe_kernel variant %d, %d blocks of 256 per CU" % (variant, bpc),
+            "copy_us": round(t * 1e3, 2), "copy_exact": ok}
+
+
 def per_config_rates(pr, W, torch, kernel_of):
     """Rate of the batched fine-step launch (all P slices in one launch) on
     every workload, timed with HIP events over a few steps on random data
@@ -228,6 +261,8 @@ def main():
     dk = [float(lg[0, k, 8] / lg[0, k, 9]) for k in range(p.K)]
     fine_variant, coarse_variant = plan.kernel_variants()
     traffic = MEASURED_TRAFFIC.get((fine_variant, args.config))
+    ceiling = copy_ceiling(pr, torch, int(bytes_per_launch) // 2)
+    log("copy ceiling", ceiling)
 
     extra = {}
     if not args.no_per_config:
@@ -390,6 +425,8 @@ def main():
                    "grid": list(p.n), "P": p.P, "K": p.K, "nt_fine": p.nt_fine, "nt_coarse": p.nt_coarse},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
+                     "achievable": ceiling["gbs"], "frac_of_achievable": round(achieved / ceiling["gbs"], 4),
+                     "achievable_probe": ceiling,
                      "kernel": "%s (%s)" % (kernel_of(fine_variant), fine_variant), "coarse_kernel": coarse_variant,
                      "avg_launch_us": round(avg_launch_s * 1e6, 2),
                      "algorithmic_bytes_per_launch": int(bytes_per_launch)},

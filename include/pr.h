@@ -188,6 +188,19 @@ int pr_defect_norm(int64_t npts, int32_t batch, int32_t xd, const void *x, int32
                    double *out4, void *ws, size_t ws_bytes, void *stream);
 size_t pr_defect_workspace_bytes(int32_t batch);
 
+
+/*
+ * pr_copy_probe -- achievable HBM bandwidth of a plain streaming kernel of
+ * this library: copies `bytes` (a positive multiple of 16; src and dst
+ * 16-byte aligned, not overlapping) from src to dst with 16-byte accesses,
+ * on blocks_per_cu (1..64, 0 = 8) blocks of 256 threads per compute unit.
+ * variant 0: four 16-byte loads in flight per thread, 1: the same with
+ * non-temporal loads and stores, 2: eight in flight, 3: one.  It is the
+ * measured ceiling of a kernel that reads once and writes once, beside the
+ * device's nominal peak.  Asynchronous on `stream`.
+ */
+int pr_copy_probe(const void *src, void *dst, size_t bytes, int32_t variant, int32_t blocks_per_cu, void *stream);
+
 /*
  * Plans and the full solve (Algorithm 1 with all slices of all instances on
  * one device; the slices are a batch dimension of F).

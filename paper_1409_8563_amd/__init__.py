@@ -213,6 +213,19 @@ def defect_norm(x, ref, batch=1, stream=None):
     return out
 
 
+def copy_probe(src, dst, variant=0, blocks_per_cu=0, stream=None):
+    """Copy src into dst (same byte count, multiple of 16) with the library's
+    bandwidth-probe kernel."""
+    _shape(src, "src")
+    _shape(dst, "dst")
+    nb = src.numel() * src.element_size()
+    if dst.numel() * dst.element_size() != nb:
+        raise ValueError("src and dst must hold the same number of bytes")
+    check(lib().pr_copy_probe(_ptr(src, "src"), _ptr(dst, "dst", like=src), nb, int(variant), int(blocks_per_cu),
+                              _stream_ptr(stream)))
+    return dst
+
+
 def check_stability(prob):
     """(status, fine_margin, coarse_margin); margins <= 1 are stable."""
     s = to_struct(prob)

@@ -24,7 +24,7 @@ EXPORTS = ["pr_last_error", "pr_version", "pr_check_stability", "pr_fine_sweep",
            "pr_plan_iterations", "pr_plan_kernel_variants", "pr_plan_fine_groups", "pr_plan_timings", "pr_plan_slice_state", "pr_set_kernel_variant",
            "pr_kernel_variant_count", "pr_kernel_variant_name", "pr_kernel_variant_info",
            "pr_autotune_workspace_bytes", "pr_autotune", "pr_plan_autotune", "pr_transfer_workspace_bytes",
-           "pr_restrict", "pr_prolong", "pr_sweep_kernel_variant"]
+           "pr_restrict", "pr_prolong", "pr_sweep_kernel_variant", "pr_copy_probe"]
 
 
 class PrError(RuntimeError):
@@ -71,6 +71,7 @@ def lib():
     L.pr_defect_norm.argtypes = [_i64, _i32, _i32, _vp, _i32, _vp, _vp, _vp, _sz, _vp]
     L.pr_defect_workspace_bytes.argtypes = [_i32]
     L.pr_defect_workspace_bytes.restype = _sz
+    L.pr_copy_probe.argtypes = [_vp, _vp, _sz, _i32, _i32, _vp]
     L.pr_plan_workspace_bytes.argtypes = [pp, _i32, _i32]
     L.pr_plan_workspace_bytes.restype = _sz
     L.pr_plan_create.argtypes = [pp, _i32, _i32, _vp, _sz, ctypes.POINTER(_vp)]

@@ -16,7 +16,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libpr.so")
-SOURCES = ["stencil_kernels.hip", "pointwise_kernels.hip", "transfer_kernels.hip", "pr_api.cpp"]
+SOURCES = ["stencil_kernels.hip", "pointwise_kernels.hip", "transfer_kernels.hip", "probe_kernels.hip", "pr_api.cpp"]
 ARCH = os.environ.get("PR_OFFLOAD_ARCH", "gfx950")
 
 

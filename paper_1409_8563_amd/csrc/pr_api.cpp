@@ -1247,6 +1247,22 @@ int pr_defect_norm(int64_t npts, int32_t batch, int32_t xd, const void *x, int32
     return defect_enqueue(npts, batch, xd, x, rd, ref, out4, items.data(), table, part, (hipStream_t)stream);
 }
 
+int pr_copy_probe(const void *src, void *dst, size_t bytes, int32_t variant, int32_t blocks_per_cu, void *stream)
+{
+    if (!src || !dst) return fail(PR_EINVAL, "NULL pointer");
+    if (bytes == 0 || bytes % 16) return fail(PR_EINVAL, "bytes must be a positive multiple of 16");
+    if (((uintptr_t)src | (uintptr_t)dst) % 16) return fail(PR_EINVAL, "buffers must be 16-byte aligned");
+    const char *a = (const char *)src, *o = (const char *)dst;
+    if (a < o + bytes && o < a + bytes) return fail(PR_EINVAL, "source and destination overlap");
+    if (variant < 0 || variant > 3) return fail(PR_EINVAL, "variant must be 0..3");
+    if (blocks_per_cu < 0 || blocks_per_cu > 64) return fail(PR_EINVAL, "blocks_per_cu must be 0..64");
+    int rc = device_ready();
+    if (rc) return rc;
+    const int blocks = g_num_cus * (blocks_per_cu ? blocks_per_cu : 8);
+    HIPCHK(pr::launch_copy_probe(variant, src, dst, bytes, blocks, (hipStream_t)stream));
+    return PR_OK;
+}
+
 size_t pr_plan_workspace_bytes(const pr_problem *probs, int32_t ninst, int32_t mode)
 {
     if (validate_plan_args(probs, ninst, mode)) return 0;

@@ -91,6 +91,10 @@ hipError_t launch_pointwise(int op, int sweep_dtype, const PointItem *items, int
 hipError_t launch_pointwise_inline(int op, int sweep_dtype, const PointItem &item, hipStream_t s);
 hipError_t launch_defect_partials(int xd, int rd, const PointItem *items, int nitems, hipStream_t s);
 hipError_t launch_defect_final(const PointItem *items, int nitems, hipStream_t s);
+// Achievable-bandwidth probe: copy `bytes` (multiple of 16) with `blocks`
+// blocks; variant 0: 4 loads in flight per thread, 1: the same with
+// non-temporal accesses, 2: 8 in flight, 3: 1 in flight.
+hipError_t launch_copy_probe(int variant, const void *src, void *dst, size_t bytes, int blocks, hipStream_t s);
 // Copy host descriptor arrays into device tables through kernel arguments
 // (stream ordered and safe to record in a graph).
 hipError_t launch_write_items(const ItemDesc *host_items, int n, ItemDesc *dev_table, hipStream_t s);

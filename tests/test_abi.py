@@ -356,3 +356,15 @@ def test_binding_rejects_mismatched_buffers_before_any_device_work():
     with pytest.raises(ValueError, match="GPU"):
         pr.parareal_update(f32(10), f32(10), f32(10))
 
+
+
+
+def test_copy_probe_validation_without_device():
+    L = _lib()
+    lib = L.lib()
+    assert lib.pr_copy_probe(None, 16, 16, 0, 0, None) == L.PR_EINVAL
+    assert lib.pr_copy_probe(16, 4096, 24, 0, 0, None) == L.PR_EINVAL      # not a multiple of 16
+    assert lib.pr_copy_probe(16, 32, 64, 0, 0, None) == L.PR_EINVAL        # overlap
+    assert lib.pr_copy_probe(8, 4096, 16, 0, 0, None) == L.PR_EINVAL       # misaligned
+    assert lib.pr_copy_probe(16, 4096, 16, 4, 0, None) == L.PR_EINVAL      # unknown variant
+    assert lib.pr_copy_probe(16, 4096, 16, 0, 65, None) == L.PR_EINVAL     # grid size
