@@ -188,6 +188,25 @@ int pr_defect_norm(int64_t npts, int32_t batch, int32_t xd, const void *x, int32
                    double *out4, void *ws, size_t ws_bytes, void *stream);
 size_t pr_defect_workspace_bytes(int32_t batch);
 
+/*
+ * pr_defect_norm_static -- pr_defect_norm without a workspace argument and
+ * without any allocation, for callers that cannot allocate device memory
+ * (code under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc).  Same arguments, results and determinism as pr_defect_norm
+ * (bitwise the same out4; same kernels).  Its descriptor table and block
+ * partials live in a library-owned device array of
+ * pr_defect_static_scratch_bytes() bytes (about 1 MiB), one per GPU, held
+ * until the process ends; it serves at most PR_DEFECT_STATIC_MAX_BATCH field
+ * pairs per call (larger batch: PR_EINVAL, nothing launched).  Every call on
+ * one GPU shares that GPU's array: calls whose work overlaps on one GPU (on
+ * different streams, or from several threads) race and must be ordered by
+ * the caller.  Nothing in the array needs clearing between calls (every
+ * partial is written before it is read).
+ */
+#define PR_DEFECT_STATIC_MAX_BATCH 64
+int pr_defect_norm_static(int64_t npts, int32_t batch, int32_t xd, const void *x, int32_t rd, const void *ref,
+                          double *out4, void *stream);
+size_t pr_defect_static_scratch_bytes(void);
 
 /*
  * pr_copy_probe -- achievable HBM bandwidth of a plain streaming kernel of

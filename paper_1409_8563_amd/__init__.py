@@ -213,6 +213,29 @@ def defect_norm(x, ref, batch=1, stream=None):
     return out
 
 
+def defect_norm_static(x, ref, batch=1, out=None, stream=None):
+    """defect_norm through the allocation-free entry point: the library's own
+    per-GPU scratch array replaces the workspace; `out` ([batch, 4] FP64) may
+    be supplied so that the call allocates nothing at all."""
+    torch = _torch()
+    xd, rd = _code(x), _code(ref)
+    batch = int(batch)
+    _shape(x, "x")
+    if batch < 1 or x.numel() == 0 or x.numel() % batch:
+        raise ValueError("x must hold a positive multiple of batch values")
+    _shape(ref, "ref", numel=x.numel())
+    n = x.numel() // batch
+    px = _ptr(x, "x")
+    pref = _ptr(ref, "ref", like=x)
+    made = out is None
+    if made:
+        out = torch.empty((batch, 4), dtype=torch.float64, device=x.device)
+    _shape(out, "out", numel=4 * batch, dtype=torch.float64)
+    check(lib().pr_defect_norm_static(n, batch, xd, px, rd, pref, _ptr(out, "out", like=x), _stream_ptr(stream)))
+    _keep_alive(stream, out if made else None)
+    return out
+
+
 def copy_probe(src, dst, variant=0, blocks_per_cu=0, stream=None):
     """Copy src into dst (same byte count, multiple of 16) with the library's
     bandwidth-probe kernel."""

@@ -12,6 +12,7 @@ LIB_PATH = os.path.join(HERE, "libpr.so")
 PR_OK, PR_EINVAL, PR_EUNSTABLE, PR_ENOMEM, PR_EDEVICE, PR_EUNSUPPORTED, PR_ENONFINITE = 0, -1, -2, -3, -4, -5, -6
 PR_FP32, PR_FP64 = 1, 2
 PR_MODE_FP64, PR_MODE_MIXED, PR_MODE_PER_SLICE, PR_MODE_GRAPH, PR_MODE_TIMED = 0, 1, 16, 32, 64
+PR_DEFECT_STATIC_MAX_BATCH = 64
 PR_NU_FROZEN, PR_ALLOW_UNSTABLE, PR_EARLY_STOP, PR_SKIP_CONVERGED, PR_COARSEN_G, PR_CUBIC_INTERP = 1, 2, 4, 8, 16, 32
 
 STATUS_NAMES = {0: "PR_OK", -1: "PR_EINVAL", -2: "PR_EUNSTABLE", -3: "PR_ENOMEM", -4: "PR_EDEVICE",
@@ -24,7 +25,8 @@ EXPORTS = ["pr_last_error", "pr_version", "pr_check_stability", "pr_fine_sweep",
            "pr_plan_iterations", "pr_plan_kernel_variants", "pr_plan_fine_groups", "pr_plan_timings", "pr_plan_slice_state", "pr_set_kernel_variant",
            "pr_kernel_variant_count", "pr_kernel_variant_name", "pr_kernel_variant_info",
            "pr_autotune_workspace_bytes", "pr_autotune", "pr_plan_autotune", "pr_transfer_workspace_bytes",
-           "pr_restrict", "pr_prolong", "pr_sweep_kernel_variant", "pr_copy_probe"]
+           "pr_restrict", "pr_prolong", "pr_sweep_kernel_variant", "pr_defect_norm_static",
+           "pr_defect_static_scratch_bytes", "pr_copy_probe"]
 
 
 class PrError(RuntimeError):
@@ -71,6 +73,9 @@ def lib():
     L.pr_defect_norm.argtypes = [_i64, _i32, _i32, _vp, _i32, _vp, _vp, _vp, _sz, _vp]
     L.pr_defect_workspace_bytes.argtypes = [_i32]
     L.pr_defect_workspace_bytes.restype = _sz
+    L.pr_defect_norm_static.argtypes = [_i64, _i32, _i32, _vp, _i32, _vp, _vp, _vp]
+    L.pr_defect_static_scratch_bytes.argtypes = []
+    L.pr_defect_static_scratch_bytes.restype = _sz
     L.pr_copy_probe.argtypes = [_vp, _vp, _sz, _i32, _i32, _vp]
     L.pr_plan_workspace_bytes.argtypes = [pp, _i32, _i32]
     L.pr_plan_workspace_bytes.restype = _sz

@@ -1247,6 +1247,51 @@ int pr_defect_norm(int64_t npts, int32_t batch, int32_t xd, const void *x, int32
     return defect_enqueue(npts, batch, xd, x, rd, ref, out4, items.data(), table, part, (hipStream_t)stream);
 }
 
+}  // extern "C"
+
+// ---- pr_defect_norm_static: the norms without a caller workspace ----------
+//
+// The item table and the block partials live in a file-scope device array
+// (one copy per GPU, held until the process ends).  In host code `scratch`
+// names a host-side stand-in, not device memory: the device address of each
+// GPU's copy is taken once per device with hipGetSymbolAddress and only that
+// address reaches the kernels.
+namespace {
+
+constexpr size_t kStaticTableBytes = ((size_t)PR_DEFECT_STATIC_MAX_BATCH * sizeof(PointItem) + 255) & ~(size_t)255;
+constexpr size_t kStaticScratchBytes =
+    kStaticTableBytes + (size_t)PR_DEFECT_STATIC_MAX_BATCH * pr::kNormBlocks * 4 * sizeof(double);
+
+__device__ __align__(256) unsigned char scratch[kStaticScratchBytes];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void *g_scratch_ptr[kMaxDevices] = {};
+
+// Device address of the current device's scratch array (looked up on the
+// first call on that device, with the device current).
+int static_scratch(void **out)
+{
+    int dev = 0;
+    HIPCHK(hipGetDevice(&dev));
+    if (dev < 0 || dev >= kMaxDevices) return fail(PR_EDEVICE, "device index %d beyond %d", dev, kMaxDevices);
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void *p = nullptr;
+        HIPCHK(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+        if (!p) return fail(PR_EDEVICE, "hipGetSymbolAddress returned NULL for the scratch array");
+        g_scratch_ptr[dev] = p;
+    }
+    *out = g_scratch_ptr[dev];
+    return PR_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+size_t pr_defect_static_scratch_bytes(void) { return kStaticScratchBytes; }
+
 int pr_copy_probe(const void *src, void *dst, size_t bytes, int32_t variant, int32_t blocks_per_cu, void *stream)
 {
     if (!src || !dst) return fail(PR_EINVAL, "NULL pointer");
@@ -1261,6 +1306,26 @@ int pr_copy_probe(const void *src, void *dst, size_t bytes, int32_t variant, int
     const int blocks = g_num_cus * (blocks_per_cu ? blocks_per_cu : 8);
     HIPCHK(pr::launch_copy_probe(variant, src, dst, bytes, blocks, (hipStream_t)stream));
     return PR_OK;
+}
+
+int pr_defect_norm_static(int64_t npts, int32_t batch, int32_t xd, const void *x, int32_t rd, const void *ref,
+                          double *out4, void *stream)
+{
+    int rc = defect_args(npts, batch, xd, x, rd, ref, out4);
+    if (rc) return rc;
+    if (batch > PR_DEFECT_STATIC_MAX_BATCH)
+        return fail(PR_EINVAL, "batch %d exceeds the %d field pairs the static scratch holds; use pr_defect_norm",
+                    batch, PR_DEFECT_STATIC_MAX_BATCH);
+    rc = device_ready();
+    if (rc) return rc;
+    void *base = nullptr;
+    rc = static_scratch(&base);
+    if (rc) return rc;
+    char *w = (char *)base;
+    PointItem *table = (PointItem *)w;
+    double *part = (double *)(w + kStaticTableBytes);
+    PointItem items[PR_DEFECT_STATIC_MAX_BATCH];   // host staging of the descriptors, no heap
+    return defect_enqueue(npts, batch, xd, x, rd, ref, out4, items, table, part, (hipStream_t)stream);
 }
 
 size_t pr_plan_workspace_bytes(const pr_problem *probs, int32_t ninst, int32_t mode)

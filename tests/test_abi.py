@@ -368,3 +368,15 @@ def test_copy_probe_validation_without_device():
     assert lib.pr_copy_probe(8, 4096, 16, 0, 0, None) == L.PR_EINVAL       # misaligned
     assert lib.pr_copy_probe(16, 4096, 16, 4, 0, None) == L.PR_EINVAL      # unknown variant
     assert lib.pr_copy_probe(16, 4096, 16, 0, 65, None) == L.PR_EINVAL     # grid size
+
+def test_static_defect_norm_validation_without_device():
+    """The allocation-free norm entry point rejects a batch beyond its static
+    scratch (and bad arguments) before any device work."""
+    L = _lib()
+    lib = L.lib()
+    assert lib.pr_defect_static_scratch_bytes() >= L.PR_DEFECT_STATIC_MAX_BATCH * 512 * 4 * 8
+    assert lib.pr_defect_norm_static(10, L.PR_DEFECT_STATIC_MAX_BATCH + 1, 2, 1, 2, 1, 1, None) == L.PR_EINVAL
+    assert "exceeds" in L.last_error()
+    assert lib.pr_defect_norm_static(0, 1, 2, 1, 2, 1, 1, None) == L.PR_EINVAL
+    assert lib.pr_defect_norm_static(10, 1, 3, 1, 2, 1, 1, None) == L.PR_EINVAL
+    assert lib.pr_defect_norm_static(10, 1, 2, None, 2, 1, 1, None) == L.PR_EINVAL
