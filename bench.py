@@ -32,11 +32,30 @@ PAPER_TABLE1 = {"nodes": [4, 8, 16, 32, 64, 128],
                 "S_measured_cpu": [1.3, 2.6, 5.0, 9.5, 17.6, 29.7],
                 "S_measured_gpu": [1.3, 2.6, 5.0, 9.3, 16.6, 26.3]}
 
-# HBM bytes per batched fused-RK4 launch measured with rocprofv3 FETCH_SIZE /
-# WRITE_SIZE (scaled by the plain-copy calibration), for the kernel variant
-# and workload they were taken on (the hbm_counters summaries).  Reported
-# only while the plan still launches that variant.
-MEASURED_TRAFFIC = {("rk4w_f64_x128_y8_p2x1_w16", "c2_128_fp64"): 558109929}
+# HBM bytes per batched fused-RK4 launch from rocprofv3 FETCH_SIZE /
+# WRITE_SIZE (scaled by the plain-copy calibration), recorded with the
+# SHA-256 of the kernel source they were taken on.  A figure is reported only
+# while the source is unchanged and the plan still launches that variant.
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "hbm_traffic.json")
+KERNEL_SOURCE = os.path.join(ROOT, "paper_1409_8563_amd", "csrc", "stencil_kernels.hip")
+
+
+def measured_traffic(variant, workload):
+    """(bytes per launch or None, note)."""
+    import hashlib
+    try:
+        with open(TRAFFIC_FILE) as f:
+            rec = json.load(f)
+    except (OSError, ValueError):
+        return None, "no recorded counters"
+    with open(KERNEL_SOURCE, "rb") as f:
+        sha = hashlib.sha256(f.read()).hexdigest()
+    if rec.get("stencil_kernels_sha256") != sha:
+        return None, "kernel source changed since the counters were taken"
+    v = rec.get("per_launch_bytes", {}).get("%s@%s" % (variant, workload))
+    if v is None:
+        return None, "no counters for this variant and workload"
+    return int(v), "rocprofv3 FETCH_SIZE + WRITE_SIZE, %s" % rec.get("summary", "profiles/")
 
 
 def kernel_of(variant):
@@ -50,22 +69,6 @@ def kernel_of(variant):
 
 def log(*a):
     print("[bench]", *a, file=sys.stderr, flush=True)
-
-
-def cpu_baseline(p, u0_np, budget_s=15.0):
-    """Time the FP64 oracle's RK4 steps on the same grid (bounded sample)."""
-    import oracle
-    oracle.lib()
-    t = time.perf_counter()
-    oracle.fine_steps(p, 0, 1, u0_np)
-    one = time.perf_counter() - t
-    m = int(max(2, min(400, budget_s / max(one, 1e-6))))
-    t = time.perf_counter()
-    oracle.fine_steps(p, 0, m, u0_np)
-    dt = time.perf_counter() - t
-    return {"value": m * p.npts / dt / 1e9, "unit": "GLUP/s", "cores": oracle.threads(), "kind": "oracle",
-            "sample": "%d FP64 RK4 steps of the oracle on one %dx%dx%d field (%.1f s)" % (m, p.n[0], p.n[1], p.n[2],
-                                                                                        dt)}
 
 
 def copy_ceiling(pr, torch, nbytes):
@@ -171,6 +174,266 @@ def per_config_rates(pr, W, torch, kernel_of):
     return out
 
 
+N_SAMPLES = 4096
+
+
+def sample_index(npts, seed=7):
+    """Fixed flat indices at which large fields are compared with the reference."""
+    import numpy as np
+    return np.sort(np.random.default_rng(seed).choice(npts, size=min(N_SAMPLES, npts), replace=False))
+
+
+def workload_solves(pr, W, torch, quick=False):
+    """Time-to-solution of every workload on the GPU, in three forms: batched
+    Parareal (FP32 sweeps for the mixed workloads, FP64 otherwise), plain
+    per-slice FP64 Parareal (one F launch per slice and step) and the serial
+    FP64 fine sweep; and the Parareal results (full field for the 32^3
+    workload, fixed sample points elsewhere) for the accuracy check against
+    the FP64 reference computed in the CPU leg.  Times: median of `reps`
+    blocking calls after one warm call (one call for the 512^3 workload)."""
+    import numpy as np
+
+    def timed(fn, reps):
+        fn()
+        torch.cuda.synchronize()
+        ts = []
+        for _ in range(reps):
+            t = time.perf_counter()
+            fn()
+            torch.cuda.synchronize()
+            ts.append((time.perf_counter() - t) * 1e3)
+        return float(np.median(ts))
+
+    out = {}
+    names = ["c1_32_fp64", "c2_128_fp64", "c3_256_mixed"] + ([] if quick else ["c5_512_mixed"])
+    for name in names:
+        p, modes = W.config(name)
+        mixed = W.MIXED[name]
+        reps = 1 if name == "c5_512_mixed" else (3 if name == "c3_256_mixed" else 5)
+        u0 = torch.from_numpy(W.synth_u0(p.n, modes)).cuda()
+        idx = None if name == "c1_32_fp64" else sample_index(p.npts)
+        idx_t = None if idx is None else torch.from_numpy(idx).cuda()
+
+        def grab(u):
+            return (u.view(-1) if idx_t is None else u.view(-1)[idx_t]).cpu().numpy()
+
+        rec = {"forms": {}}
+        uT = torch.empty_like(u0)
+        mode = pr.PR_MODE_MIXED if mixed else pr.PR_MODE_FP64
+        plan = pr.Plan([p], mode)
+        t = timed(lambda: plan.solve([u0], uT=[uT], want_log=False), reps)
+        rec["forms"]["parareal_batched_" + ("fp32_sweeps" if mixed else "fp64")] = {"ms": round(t, 3),
+                                                                                  "result": grab(uT)}
+        del plan
+        torch.cuda.empty_cache()
+        plan = pr.Plan([p], pr.PR_MODE_FP64 | pr.PR_MODE_PER_SLICE)
+        t = timed(lambda: plan.solve([u0], uT=[uT], want_log=False), reps)
+        rec["forms"]["parareal_plain_fp64_per_slice"] = {"ms": round(t, 3), "result": grab(uT)}
+        del plan
+        torch.cuda.empty_cache()
+        t = timed(lambda: pr.fine_sweep(p, u0, 0, p.nt_fine, u_out=uT), reps)
+        rec["forms"]["serial_fine_fp64"] = {"ms": round(t, 3), "result": grab(uT)}
+        rec["idx"] = idx
+        out[name] = rec
+        del u0, uT
+        torch.cuda.empty_cache()
+        log("solved", name, {k: v["ms"] for k, v in rec["forms"].items()})
+
+    # the 64 uneven instances: one plan over all of them
+    insts = W.batched_config(64)
+    probs = [q for q, _ in insts]
+    u0s = [torch.from_numpy(W.synth_u0(q.n, m)).cuda() for q, m in insts]
+    uTs = [torch.empty_like(u) for u in u0s]
+    idxs = [sample_index(q.npts, seed=11 + i) for i, q in enumerate(probs)]
+    idx_ts = [torch.from_numpy(i).cuda() for i in idxs]
+
+    def grab_all():
+        return [u.view(-1)[i].cpu().numpy() for u, i in zip(uTs, idx_ts)]
+
+    rec = {"forms": {}, "idx": idxs}
+    plan = pr.Plan(probs, pr.PR_MODE_MIXED)
+    t = timed(lambda: plan.solve(u0s, uT=uTs, want_log=False), 3)
+    rec["forms"]["parareal_batched_fp32_sweeps"] = {"ms": round(t, 3), "result": grab_all()}
+    del plan
+    torch.cuda.empty_cache()
+    plan = pr.Plan(probs, pr.PR_MODE_FP64 | pr.PR_MODE_PER_SLICE)
+    t = timed(lambda: plan.solve(u0s, uT=uTs, want_log=False), 1)
+    rec["forms"]["parareal_plain_fp64_per_slice"] = {"ms": round(t, 3), "result": grab_all()}
+    del plan
+    torch.cuda.empty_cache()
+
+    def serial_all():
+        for q, u, o in zip(probs, u0s, uTs):
+            pr.fine_sweep(q, u, 0, q.nt_fine, u_out=o)
+    t = timed(serial_all, 1)
+    rec["forms"]["serial_fine_fp64"] = {"ms": round(t, 3), "result": grab_all(),
+                                        "note": "the 64 instances one after another on one stream"}
+    out["c4_batched_64"] = rec
+    log("solved c4_batched_64", {k: v["ms"] for k, v in rec["forms"].items()})
+    del u0s, uTs
+    torch.cuda.empty_cache()
+    return out
+
+
+def lscpu_summary():
+    """Model, sockets, cores and threads of the host (lscpu), for the CPU leg."""
+    import subprocess
+    info = {}
+    try:
+        txt = subprocess.run(["lscpu"], capture_output=True, text=True, timeout=10).stdout
+    except (OSError, subprocess.SubprocessError):
+        return {"lscpu": "unavailable"}
+    for line in txt.splitlines():
+        k, _, v = line.partition(":")
+        k = k.strip()
+        if k in ("Model name", "Socket(s)", "Core(s) per socket", "Thread(s) per core", "CPU(s)", "L3 cache",
+                 "NUMA node(s)"):
+            info[k] = v.strip()
+    info["usable_threads"] = len(os.sched_getaffinity(0))
+    return info
+
+
+def cpu_leg(p_main, u0_np, solves, budget_s=8.0):
+    """The CPU leg: the FP64 oracle timed on this host, and the FP64
+    references of the workloads' results.
+
+    * cpu_baseline value: the oracle's RK4 steps on one field of the timed
+      workload, on all host threads (bounded sample).
+    * per workload: wall time of one oracle fine step and one coarse step on
+      1 thread and on 8 threads, and the oracle's Parareal and serial-fine
+      wall times extrapolated from them (the 32^3 workload's are measured
+      end to end instead).
+    * accuracy: max-abs and relative-L2 error of every GPU result against the
+      FP64 reference of the same computation: the grid oracle over the full
+      field for the 32^3 workload, elsewhere the oracle's per-Fourier-mode
+      model of the same discrete scheme (equal to the grid oracle up to
+      rounding, pinned by the tests) at fixed sample points."""
+    import numpy as np
+    import oracle
+    from oracle import spectral
+    import workloads as W
+    oracle.lib()
+    all_threads = oracle.threads()
+
+    t = time.perf_counter()
+    oracle.fine_steps(p_main, 0, 1, u0_np)
+    one = time.perf_counter() - t
+    m = int(max(2, min(400, budget_s / max(one, 1e-6))))
+    t = time.perf_counter()
+    oracle.fine_steps(p_main, 0, m, u0_np)
+    dt = time.perf_counter() - t
+    base = {"value": m * p_main.npts / dt / 1e9, "unit": "GLUP/s", "cores": all_threads, "kind": "oracle",
+            "sample": "%d FP64 RK4 steps of the oracle on one %dx%dx%d field (%.1f s) on %d host threads"
+                      % (m, p_main.n[0], p_main.n[1], p_main.n[2], dt, all_threads),
+            "host": lscpu_summary()}
+
+    def step_times(p, u, threads):
+        oracle.set_threads(threads)
+        t0 = time.perf_counter()
+        oracle.fine_steps(p, 0, 1, u)
+        tf = time.perf_counter() - t0
+        t0 = time.perf_counter()
+        oracle.coarse_steps(p, 0, 1, u)
+        tc = time.perf_counter() - t0
+        return tf, tc
+
+    per = {}
+    for name in ("c1_32_fp64", "c2_128_fp64", "c3_256_mixed", "c5_512_mixed"):
+        p, modes = W.config(name)
+        u0 = W.synth_u0(p.n, modes)
+        entry = {}
+        for th in (1, 8):
+            if name == "c1_32_fp64":
+                oracle.set_threads(th)
+                t0 = time.perf_counter()
+                U, _ = oracle.parareal(p, u0, K=p.K)
+                tp = time.perf_counter() - t0
+                t0 = time.perf_counter()
+                oracle.serial_fine(p, u0)
+                ts = time.perf_counter() - t0
+                entry["threads_%d" % th] = {"parareal_s": round(tp, 3), "serial_fine_s": round(ts, 3),
+                                            "how": "measured end to end"}
+                ref = U[-1].ravel()
+            else:
+                # the 256^3 and 512^3 grids are timed on a slab of 32 z planes
+                # (same per-point work) and scaled by n_z / 32
+                nzs = min(p.n[2], 32)
+                ps = W.Problem(**{**p.__dict__, "n": (p.n[0], p.n[1], nzs)})
+                tf, tc = step_times(ps, u0[:nzs] if nzs == p.n[2] else W.synth_u0(ps.n, modes), th)
+                tf, tc = tf * p.n[2] / nzs, tc * p.n[2] / nzs
+                tp = p.K * p.P * p.nf * tf + (p.K + 1) * p.P * p.nc * tc
+                how = ("extrapolated from one timed fine and one timed coarse step%s: K*P*Nf fine + (K+1)*P*Nc "
+                       "coarse steps" % ("" if nzs == p.n[2] else
+                                        " on a %dx%dx%d slab, scaled by n_z" % (p.n[0], p.n[1], nzs)))
+                entry["threads_%d" % th] = {"fine_step_s": round(tf, 4), "coarse_step_s": round(tc, 4),
+                                            "parareal_s": round(tp, 1), "serial_fine_s": round(p.nt_fine * tf, 1),
+                                            "how": how}
+        oracle.set_threads(all_threads)
+        if name != "c1_32_fp64":
+            sol = spectral.ModalSolution(p, modes)
+            idx = solves[name]["idx"] if name in solves else None
+            ref = sol.iterate_points(p.K, p.P, idx) if idx is not None else None
+        entry["reference"] = ("grid oracle, full field" if name == "c1_32_fp64" else
+                              "oracle per-mode model, %d sampled points" % N_SAMPLES)
+        if name in solves and ref is not None:
+            entry["accuracy_vs_fp64_parareal"] = {
+                form: errs(rec["result"], ref) for form, rec in solves[name]["forms"].items()
+                if form.startswith("parareal")}
+            fine_ref = (oracle.serial_fine(p, u0).ravel() if name == "c1_32_fp64" else
+                        sol.serial_fine_points(solves[name]["idx"]))
+            entry["accuracy_vs_fp64_serial_fine"] = {
+                form: errs(rec["result"], fine_ref) for form, rec in solves[name]["forms"].items()}
+        per[name] = entry
+        log("cpu leg", name, entry)
+    if "c4_batched_64" in solves:
+        insts = W.batched_config(64)
+        rec = solves["c4_batched_64"]
+        worst = {}
+        worst_fine = {}
+        for i, (q, modes) in enumerate(insts):
+            sol = spectral.ModalSolution(q, modes)
+            r = sol.iterate_points(q.K, q.P, rec["idx"][i])
+            rf = sol.serial_fine_points(rec["idx"][i])
+            for form, fr in rec["forms"].items():
+                for tgt, rr in ((worst, r), (worst_fine, rf)):
+                    if tgt is worst and not form.startswith("parareal"):
+                        continue
+                    e = errs(fr["result"][i], rr)
+                    w = tgt.setdefault(form, {"max_abs": 0.0, "rel_l2": 0.0})
+                    w["max_abs"] = max(w["max_abs"], e["max_abs"])
+                    w["rel_l2"] = max(w["rel_l2"], e["rel_l2"])
+        sizes = sorted({q.n[0] for q, _ in insts})
+        c4 = {"reference": "oracle per-mode model per instance, %d sampled points each; worst instance"
+                           % N_SAMPLES,
+              "accuracy_vs_fp64_parareal": worst, "accuracy_vs_fp64_serial_fine": worst_fine}
+        for th in (1, 8):
+            tot_p = tot_s = 0.0
+            cache = {}
+            for q, modes in insts:
+                if q.n[0] not in cache:
+                    cache[q.n[0]] = step_times(q, W.synth_u0(q.n, modes), th)
+                tf, tc = cache[q.n[0]]
+                tot_p += q.K * q.P * q.nf * tf + (q.K + 1) * q.P * q.nc * tc
+                tot_s += q.nt_fine * tf
+            c4["threads_%d" % th] = {"parareal_s": round(tot_p, 1), "serial_fine_s": round(tot_s, 1),
+                                     "how": "extrapolated per instance from one timed fine and coarse step of "
+                                            "each grid size %s" % sizes}
+        oracle.set_threads(all_threads)
+        per["c4_batched_64"] = c4
+        log("cpu leg c4", c4)
+    base["per_workload"] = per
+    return base
+
+
+def errs(x, r):
+    import numpy as np
+    x = np.asarray(x, dtype=np.float64)
+    r = np.asarray(r, dtype=np.float64)
+    d = x - r
+    return {"max_abs": float("%.3e" % np.max(np.abs(d))),
+            "rel_l2": float("%.3e" % np.sqrt(np.sum(d * d) / np.sum(r * r)))}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -179,8 +442,9 @@ def main():
     ap.add_argument("--config", default="c2_128_fp64")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-compare", action="store_true")
-    ap.add_argument("--mixed-config", default="c3_256_mixed",
-                    help="workload of the batched-FP32 vs plain-per-slice-FP64 comparison ('' to skip)")
+    ap.add_argument("--no-solves", action="store_true",
+                    help="skip the per-workload time-to-solution and accuracy section")
+    ap.add_argument("--quick", action="store_true", help="leave the 512^3 workload out of that section")
     ap.add_argument("--no-per-config", action="store_true",
                     help="skip the per-workload F kernel rates (all five workloads)")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
@@ -260,7 +524,7 @@ def main():
     achieved = bytes_per_launch / avg_launch_s / 1e9
     dk = [float(lg[0, k, 8] / lg[0, k, 9]) for k in range(p.K)]
     fine_variant, coarse_variant = plan.kernel_variants()
-    traffic = MEASURED_TRAFFIC.get((fine_variant, args.config))
+    traffic, traffic_note = measured_traffic(fine_variant, args.config)
     ceiling = copy_ceiling(pr, torch, int(bytes_per_launch) // 2)
     log("copy ceiling", ceiling)
 
@@ -363,47 +627,28 @@ def main():
                 "defect_dk": [float("%.3e" % (lg_c[0, k, 8] / lg_c[0, k, 9])) for k in range(q.K)]}
         extra["coarsened_G"] = {"plain_G_over_F_per_slice": round(g_slice_plain / f_slice, 4), **coarsened}
         log("comparisons", extra)
-        if args.mixed_config:
-            # batched FP32-sweep Parareal against plain per-slice FP64 Parareal on
-            # the same workload.  Errors are taken on the device against the FP64
-            # serial fine solution of the library's own FP64 path (that path is
-            # checked against the CPU oracle by the parity tests), and between the
-            # two Parareal results (the FP32 sweeps' own rounding).
-            pm, mm = W.config(args.mixed_config)
-            um = torch.from_numpy(W.synth_u0(pm.n, mm)).cuda()
-            u_fine64 = pr.fine_sweep(pm, um, 0, pm.nt_fine)
-            uT_mixed = torch.empty_like(um)
-            uT_plain = torch.empty_like(um)
-
-            def errs(x, r):
-                o = pr.defect_norm(x, r).cpu().numpy()[0]
-                return {"max_abs": float("%.3e" % o[0]), "rel_l2": float("%.3e" % np.sqrt(o[2] / o[3]))}
-
-            plan_m = pr.Plan([pm], pr.PR_MODE_MIXED)
-            t_m = timed(lambda: plan_m.solve([um], uT=[uT_mixed], want_log=False), reps=3, warm=1)
-            del plan_m
-            torch.cuda.empty_cache()
-            plan_p = pr.Plan([pm], pr.PR_MODE_FP64 | pr.PR_MODE_PER_SLICE)
-            t_p = timed(lambda: plan_p.solve([um], uT=[uT_plain], want_log=False), reps=3, warm=1)
-            del plan_p
-            torch.cuda.empty_cache()
-            extra["mixed_vs_plain_fp64"] = {
-                "workload": "%s: %dx%dx%d, P=%d, K=%d, %d fine / %d coarse steps" % (
-                    args.mixed_config, pm.n[0], pm.n[1], pm.n[2], pm.P, pm.K, pm.nt_fine, pm.nt_coarse),
-                "batched_fp32_sweeps_ms": round(t_m, 2), "plain_fp64_per_slice_ms": round(t_p, 2),
-                "speedup": round(t_p / t_m, 3),
-                "error_vs_fp64_serial_fine": {"batched_fp32_sweeps": errs(uT_mixed, u_fine64),
-                                              "plain_fp64_per_slice": errs(uT_plain, u_fine64)},
-                "batched_fp32_vs_plain_fp64_parareal": errs(uT_mixed, uT_plain)}
-            del um, u_fine64, uT_mixed, uT_plain
-            torch.cuda.empty_cache()
-            log("mixed comparison", extra["mixed_vs_plain_fp64"])
-
+    solves = {}
+    if not args.no_solves:
+        solves = workload_solves(pr, W, torch, quick=args.quick)
     cpu = None
     if not args.no_cpu_baseline:
-        log("cpu baseline (oracle) ...")
-        cpu = cpu_baseline(p, u0_np)
-        log("cpu baseline", cpu)
+        log("cpu leg (oracle) ...")
+        cpu = cpu_leg(p, u0_np, solves)
+        log("cpu baseline", {k: v for k, v in cpu.items() if k != "per_workload"})
+    if solves:
+        wl = {}
+        for name, rec in solves.items():
+            e = {"time_to_solution_ms": {form: r["ms"] for form, r in rec["forms"].items()}}
+            if cpu is not None and name in cpu["per_workload"]:
+                c = cpu["per_workload"][name]
+                for key in ("reference", "accuracy_vs_fp64_parareal", "accuracy_vs_fp64_serial_fine"):
+                    if key in c:
+                        e[key] = c[key]
+                e["oracle_wall_s"] = {k: v for k, v in c.items() if k.startswith("threads_")}
+            wl[name] = e
+        extra["workloads"] = wl
+    if cpu is not None:
+        cpu.pop("per_workload", None)
 
     line = {
         "metric": "fine-sweep GLUP/s + % peak HBM GB/s; Parareal time-to-solution vs plain FP64",
@@ -424,7 +669,7 @@ def main():
                                                            "FP32 sweeps + FP64 correction" if mixed else "FP64"),
                    "grid": list(p.n), "P": p.P, "K": p.K, "nt_fine": p.nt_fine, "nt_coarse": p.nt_coarse},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
+                     "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic, "traffic_source": traffic_note,
                      "achievable": ceiling["gbs"], "frac_of_achievable": round(achieved / ceiling["gbs"], 4),
                      "achievable_probe": ceiling,
                      "kernel": "%s (%s)" % (kernel_of(fine_variant), fine_variant), "coarse_kernel": coarse_variant,

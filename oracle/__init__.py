@@ -72,6 +72,8 @@ def lib():
         L.or_prolong.argtypes = [pp, ctypes.c_int, _dp, _dp]
         L.or_prolong.restype = None
         L.or_threads.restype = ctypes.c_int
+        L.or_set_threads.argtypes = [ctypes.c_int]
+        L.or_set_threads.restype = None
         for f in ("or_rk4_step_alloc", "or_euler_step_alloc", "or_fine_steps", "or_coarse_steps",
                   "or_serial_fine", "or_serial_coarse", "or_parareal"):
             getattr(L, f).restype = ctypes.c_int
@@ -126,6 +128,11 @@ def prolong(p, uc, order: int = 1) -> np.ndarray:
 def threads() -> int:
     """OpenMP threads used by the oracle's z loops."""
     return int(lib().or_threads())
+
+
+def set_threads(n: int) -> None:
+    """Run the oracle's z loops on n threads from now on (same results)."""
+    lib().or_set_threads(int(n))
 
 
 def nu(p, t: float) -> float:

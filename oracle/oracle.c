@@ -69,6 +69,16 @@ int or_threads(void)
 #endif
 }
 
+/* Set the number of threads of the z loops (results do not depend on it). */
+void or_set_threads(int n)
+{
+#ifdef _OPENMP
+    if (n > 0) omp_set_num_threads(n);
+#else
+    (void)n;
+#endif
+}
+
 static long npts_of(const or_prob *p) { return (long)p->nx * p->ny * p->nz; }
 
 static int wrap(int i, int n)

@@ -68,6 +68,19 @@ __device__ __forceinline__ void gst(void *p, const V &v)
     *(PR_GLOBAL E *)p = e;
 }
 
+// Store with the non-temporal hint: the output of a step is not read again
+// by this launch, so it need not displace the input planes (which the
+// neighbouring tiles re-read for their halos) from the caches.
+template <typename V>
+__device__ __forceinline__ void gst_nt(void *p, const V &v)
+{
+    using E = typename VecTraits<V>::E;
+    E e;
+#pragma unroll
+    for (int i = 0; i < VecTraits<V>::n; ++i) e[i] = v.v[i];
+    __builtin_nontemporal_store(e, (PR_GLOBAL E *)p);
+}
+
 __device__ __forceinline__ int wrapi(int i, int n)
 {
     int r = i % n;
@@ -1116,7 +1129,7 @@ __global__ void __launch_bounds__(64 * NW)
 #pragma unroll
                     for (int ix = 0; ix < NXP; ++ix)
                         v.v[ix] = fmaT(kc.b4, S[iy][ix], ac[slot<L>(M, 4)][iy][ix]);
-                    gst<Vec<T, NXP>>(obase + rowoff[iy], v);
+                    gst_nt<Vec<T, NXP>>(obase + rowoff[iy], v);
                 }
             }
         };

@@ -150,3 +150,21 @@ def test_analytic_matches_paper_decay_factor():
     integral = 0.1 * t - 0.1 / (2 * 100.0) * (math.cos(100.0 * t) - 1.0)
     fac = math.exp(-12 * math.pi ** 2 * integral)
     assert np.max(np.abs(u - fac * u0)) <= 1e-14
+
+
+def test_thread_count_does_not_change_results(orc):
+    """The oracle's z loops give bitwise the same fields on 1 thread and on
+    several (each output point is computed by the same operations), so its
+    single- and multi-thread wall times time the same computation."""
+    p = W.small_problem(n=(9, 7, 12), P=3, nf=2, nc=2, K=2)
+    u0 = W.random_field(p.n, 33)
+    default = orc.threads()
+    try:
+        orc.set_threads(1)
+        assert orc.threads() == 1
+        U1, log1 = orc.parareal(p, u0)
+        orc.set_threads(4)
+        U4, log4 = orc.parareal(p, u0)
+    finally:
+        orc.set_threads(default)
+    assert np.array_equal(U1, U4) and np.array_equal(log1, log4)
