@@ -281,7 +281,9 @@ int pick_fine_default(const pr_problem &p, int dtype, int batch)
     const bool even = p.n[0] % 2 == 0;
     const char *name;
     if (dtype == PR_FP64)
-        name = order == 4 ? (even ? "rk4_f64_o4_t32x16_p2x1" : "rk4_f64_o4_t24x8_p1x1")
+        name = order == 4 ? (p.n[0] == 128 ? "rk4h_f64_o4_x128_y8_p2_w16_d1"
+                             : even          ? "rk4_f64_o4_t32x16_p2x1"
+                                             : "rk4_f64_o4_t24x8_p1x1")
                : p.n[0] == 128 ? "rk4w_f64_x128_y8_p2x1_w16"
                : p.n[0] == 64  ? (batch >= 4 ? "rk4w_f64_x64_y16_p1x2_w12" : "rk4w_f64_x64_y8_p1x2_w8")
                                : "rk4b_f64_t32x32_p1x2_d2";
@@ -307,7 +309,9 @@ int pick_fine_default(const pr_problem &p, int dtype, int batch)
         }
         return best_v;
     } else
-        name = order == 4 ? (even ? "rk4r_f32_o4_t32x16_p2x2_d2" : "rk4_f32_o4_t32x16_p1x2")
+        name = order == 4 ? (p.n[0] == 128 ? "rk4h_f32_o4_x128_y8_p2_w16"
+                             : even          ? "rk4r_f32_o4_t32x16_p2x2_d2"
+                                             : "rk4_f32_o4_t32x16_p1x2")
                : p.n[0] == 256 ? "rk4w_f32_x256_y8_p4x2_w8"
                : p.n[0] == 128 ? (batch >= 4 ? "rk4w_f32_x128_y16_p2x2_w12" : "rk4w_f32_x128_y8_p2x2_w8")
                                : "rk4b_f32_t32x32_p1x4_d2";
@@ -442,10 +446,16 @@ int coarse_steps_per_launch(int v) { return v >= 2 ? pr::coarse_variant(v)->step
 
 // ---- sweeps -----------------------------------------------------------------
 
+// Scratch fields per item (3 per field of the batch) are reserved for the
+// unfused reference kernels and for every fourth-order problem, whose fine
+// variants may take two launches per step through them.
+bool scratch_reserved(const pr_problem &p, bool fine_ref) { return fine_ref || p.fine_order == 4; }
+
 size_t sweep_ws(const pr_problem &p, int dtype, int batch, bool fine_ref)
 {
     const size_t states = (size_t)batch * npts_of(p) * esize(dtype);
-    return align256((size_t)batch * sizeof(ItemDesc)) + align256(states) + (fine_ref ? 3 * align256(states) : 0);
+    return align256((size_t)batch * sizeof(ItemDesc)) + align256(states) +
+           (scratch_reserved(p, fine_ref) ? 3 * align256(states) : 0);
 }
 
 int sweep_common(const pr_problem *prob_in, int dtype, int batch, const void *u_in, void *u_out,
@@ -642,7 +652,7 @@ size_t plan_layout(const pr_problem *probs, int ninst, int mode, char *base, pr_
         in.Gold[0] = take(p.P * n * es);
         in.Gold[1] = take(p.P * n * es);
         in.Gtmp = take(n * es);
-        in.Fscr = fine_ref ? take(3 * p.P * n * es) : nullptr;
+        in.Fscr = scratch_reserved(p, fine_ref) ? take(3 * p.P * n * es) : nullptr;
         const bool crs = (p.flags & PR_COARSEN_G) != 0;
         in.Cin = crs ? take(n / 8 * es) : nullptr;
         in.Cout = crs ? take(n / 8 * es) : nullptr;
@@ -744,9 +754,11 @@ int build_tables(pr_plan *pl)
     const int K = pl->K;
     const VariantInfo *cvi = coarse_info(pl->coarse_v);
     const bool cref = pl->coarse_v == 1;
-    for (int i = 0; i < ninst; ++i)
-        if (pl->fgroups[pl->inst_group[i]].v == 1 && !pl->inst[i].Fscr)
+    for (int i = 0; i < ninst; ++i) {
+        const int v = pl->fgroups[pl->inst_group[i]].v;
+        if ((v == 1 || fine_info(v)->scratch > 0) && !pl->inst[i].Fscr)
             return fail(PR_EINVAL, "kernel variant changed between workspace query and plan creation");
+    }
 
     pl->slice_base.resize(ninst);
     for (int i = 0, b = 0; i < ninst; ++i) {

@@ -16,7 +16,7 @@ struct ItemDesc {
     const void *src0;     // input field (read by the first step/chunk)
     void *dst;            // output of the last step/chunk
     void *tmp;            // ping-pong partner of dst (unused when one launch suffices)
-    void *scratch;        // 3 fields of stage storage for the unfused reference kernels
+    void *scratch;        // 3 fields of stage storage (unfused reference kernels, two-launch RK4 steps)
     int64_t step0;        // global index of the first step
     int32_t nsteps;       // steps of this sweep
     int32_t nx, ny, nz;
@@ -66,6 +66,7 @@ struct VariantInfo {
     int threads;
     int steps;            // coarse: Euler steps fused per launch
     int rowx = 0;         // nonzero: whole-row kernel, n_x must equal rowx (= tx, one tile in x)
+    int scratch = 0;      // fields of per-item scratch (ItemDesc::scratch) the kernel uses
 };
 int fine_variant_count();
 const VariantInfo *fine_variant(int v);      // v >= 2

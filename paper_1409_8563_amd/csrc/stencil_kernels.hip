@@ -1172,6 +1172,238 @@ __global__ void __launch_bounds__(64 * NW)
     }
 }
 // ---------------------------------------------------------------------------
+// Half of an RK4 step over whole x rows for stencils of radius R (R <= NXP),
+// two stages per launch.  Four fused stages of a radius-2 stencil need a
+// halo of 8 rows and 8 planes per side, whose register rings do not fit one
+// CU; two fused stages need a halo of 4, the same as four radius-1 stages.
+//   HALF 0: stages 1 and 2 from u; writes y2 = u + c2 k2 and the partial sum
+//           a2 = (u + b1 k1) + b2 k2 to the item's scratch fields 0 and 1.
+//   HALF 1: stages 3 and 4 from y2 (stencil input), u and a2 (pointwise);
+//           writes the step's output.
+// The per-point arithmetic is that of the fused kernels (same apply(), same
+// fused multiply-adds in the same order), so the result is bitwise the same.
+// Layout as rk4_step_rows with one row per lane (NY = 1): every row of the
+// stage inputs is exchanged through LDS.  Stage s of the half evaluates plane
+// p - sR in iteration p; the plane that stage s + 1 reads in iteration p + 1
+// was computed in iteration p - 1, so every LDS put happens at the top of
+// the iteration, into the slot of this iteration's parity, and one barrier
+// per plane orders the puts before the reads of the next iteration.
+// ---------------------------------------------------------------------------
+template <typename T, int R, int NXP, int NW, int PD, int HALF>
+__global__ void __launch_bounds__(64 * NW)
+    rk4_half_rows(const ItemDesc *__restrict__ items, int nitems, int jstep)
+{
+    static_assert(R >= 2 && R <= NXP, "radius 2..NXP: x neighbours in the adjacent lanes, and the plane that "
+                                      "stage B reads next was computed an iteration earlier");
+    constexpr int H = 2 * R;              // halo of two stages (rows and planes per side)
+    constexpr int NX = 64 * NXP;
+    constexpr int EY = NW, TY = EY - 2 * H;
+    constexpr int L = 6;                  // z-ring length: even, >= 2R + 1
+    static_assert(L >= 2 * R + 1 && L % 2 == 0 && L % PD == 0, "ring length");
+    static_assert(TY > 0, "tile too small for the halo");
+    __shared__ __align__(16) T lds[2][2][NW][NX];   // [stage input][slot][wavefront = row][x]
+
+    const int lb = xcd_remap((int)blockIdx.x, (int)gridDim.x);
+    const ItemDesc &it = items[find_item(items, nitems, lb)];
+    if (jstep >= it.nsteps || it.nx != NX) return;
+    const int local = lb - it.block_begin;
+    if (local < 0 || local >= it.nblocks) return;
+
+    const int ny = it.ny, nz = it.nz;
+    const int tyt = local % it.tiles_y;
+    const int zc = local / it.tiles_y;
+    const int y0 = tyt * TY;
+    const int z0 = zc * it.tz;
+    const int zend = min(z0 + it.tz, nz);
+    const int nxy = NX * ny;
+    const size_t npts = (size_t)nxy * nz;
+
+    const T *src;
+    T *dst;
+    pingpong<T>(it, jstep, it.nsteps, src, dst);
+    T *const scr_y = (T *)it.scratch;           // y2 (stage 2 output)
+    T *const scr_a = (T *)it.scratch + npts;    // a2 (partial RK4 sum after stage 2)
+
+    const int lane = (int)threadIdx.x & 63;
+    const int wv = __builtin_amdgcn_readfirstlane((int)threadIdx.x >> 6);   // = tile row
+    const int cx0 = lane * NXP;
+    const int rowoff = wrapi(y0 - H + wv, ny) * NX + cx0;
+    const bool rowout = (wv >= H) && (wv < H + TY) && (y0 + wv - H < ny);
+    // stage s of the half can feed an output point only on rows sR .. EY-1-sR
+    const bool act1 = wv >= R && wv < EY - R, act2 = wv >= 2 * R && wv < EY - 2 * R;
+    int wn[2][R];   // wavefronts holding rows wv -/+ k (clamped; only active stages read them)
+#pragma unroll
+    for (int k = 0; k < R; ++k) {
+        wn[0][k] = max(wv - k - 1, 0);
+        wn[1][k] = min(wv + k + 1, NW - 1);
+    }
+
+    const double dt = it.dt;
+    const double t = (double)(it.step0 + jstep) * dt;
+    const double nu1 = nu_at(it, t);
+    const double nu2 = it.frozen ? nu1 : nu_at(it, t + 0.5 * dt);
+    const double nu4 = it.frozen ? nu1 : nu_at(it, t + dt);
+    const Wts<T, R> wA = uni(fine_weights<T, R>(it, HALF == 0 ? nu1 : nu2));
+    const Wts<T, R> wB = uni(fine_weights<T, R>(it, HALF == 0 ? nu2 : nu4));
+    RK4Consts<T> kc = rk4_consts<T>(dt);
+    // stage constants of this half: y = u + cA S_A, a = fma(bA, S_A, a'), then bB for S_B
+    const T cA = uni(HALF == 0 ? kc.c1 : kc.c3);
+    const T bA = uni(HALF == 0 ? kc.b1 : kc.b3);
+    const T cB = uni(kc.c2);
+    const T bB = uni(HALF == 0 ? kc.b2 : kc.b4);
+
+    // rings: in = stencil input of stage A (u, or y2), mid = output of stage A
+    // (y1, or y3), acc = partial sums after stage A; for HALF 1 also u and a2
+    T in[L][NXP], mid[L][NXP], acc[L][NXP];
+    T pin[PD][NXP];
+    // HALF 1 only: u and a2 of the plane stage A evaluates, loaded one
+    // iteration ahead (double buffered by iteration parity)
+    T pu[2][NXP], pa[2][NXP];
+
+    const T *in_src = HALF == 0 ? src : scr_y;
+    auto load_plane = [&](const T *base, int pz, T(&d)[NXP]) {
+        const Vec<T, NXP> v = gld<Vec<T, NXP>>(base + (size_t)wrapi(pz, nz) * nxy + rowoff);
+#pragma unroll
+        for (int ix = 0; ix < NXP; ++ix) d[ix] = v.v[ix];
+    };
+    auto put = [&](auto Bc, auto SLc, const T(&v)[NXP]) {
+        constexpr int B = decltype(Bc)::value;
+        constexpr int SL = decltype(SLc)::value;
+        Vec<T, NXP> a;
+#pragma unroll
+        for (int ix = 0; ix < NXP; ++ix) a.v[ix] = v[ix];
+        *reinterpret_cast<Vec<T, NXP> *>(&lds[B][SL][wv][cx0]) = a;
+    };
+    struct Nb {
+        Vec<T, NXP> m[R], p[R];   // rows wv-k-1 and wv+k+1
+    };
+    auto fetch = [&](auto Bc, auto SLc) {
+        constexpr int B = decltype(Bc)::value;
+        constexpr int SL = decltype(SLc)::value;
+        Nb nb;
+#pragma unroll
+        for (int k = 0; k < R; ++k) {
+            nb.m[k] = *reinterpret_cast<const Vec<T, NXP> *>(&lds[B][SL][wn[0][k]][cx0]);
+            nb.p[k] = *reinterpret_cast<const Vec<T, NXP> *>(&lds[B][SL][wn[1][k]][cx0]);
+        }
+        return nb;
+    };
+    // S = L(f) at the plane in ring slot SC; z neighbours at slots SC -/+ k
+    auto stencil = [&](const Nb &nb, const T(&f)[L][NXP], auto SCc, const Wts<T, R> &w, T(&S)[NXP]) {
+        constexpr int SC = decltype(SCc)::value;
+        T left[NXP], right[NXP];   // the values of lanes l-1 and l+1 (mod 64)
+#pragma unroll
+        for (int ix = 0; ix < NXP; ++ix) {
+            left[ix] = wave_rot<kDppWaveRor1>(f[SC][ix]);
+            right[ix] = wave_rot<kDppWaveRol1>(f[SC][ix]);
+        }
+#pragma unroll
+        for (int ix = 0; ix < NXP; ++ix) {
+            T mn[3][R], pn[3][R];
+#pragma unroll
+            for (int k = 0; k < R; ++k) {
+                const int im = ix - k - 1, ip = ix + k + 1;
+                mn[0][k] = im >= 0 ? f[SC][im] : left[NXP + im];
+                pn[0][k] = ip < NXP ? f[SC][ip] : right[ip - NXP];
+                mn[1][k] = nb.m[k].v[ix];
+                pn[1][k] = nb.p[k].v[ix];
+                mn[2][k] = f[(SC - k - 1 + 2 * L) % L][ix];
+                pn[2][k] = f[(SC + k + 1) % L][ix];
+            }
+            S[ix] = apply<T, R>(w, f[SC][ix], mn, pn);
+        }
+    };
+
+    auto body = [&](auto Mc, auto FASTc, int p) __attribute__((always_inline)) {
+        constexpr int M = decltype(Mc)::value;
+        constexpr bool FAST = decltype(FASTc)::value;
+        constexpr int WS = M & 1, RS = (M + 1) & 1;
+        constexpr int S0 = slot<L>(M, 0);          // plane p
+        constexpr int SA = slot<L>(M, R);          // plane p - R: stage A's centre
+        constexpr int SB = slot<L>(M, 2 * R);      // plane p - 2R: stage B's centre
+        __syncthreads();
+#pragma unroll
+        for (int ix = 0; ix < NXP; ++ix) in[S0][ix] = pin[M % PD][ix];
+        load_plane(in_src, p + PD, pin[M % PD]);
+        if constexpr (HALF == 1) {
+            // u and a2 at plane p + 1 - R, for stage A of the next iteration
+            load_plane(src, p + 1 - R, pu[M & 1]);
+            load_plane(scr_a, p + 1 - R, pa[M & 1]);
+        }
+        // planes read by the stages of iteration p + 1: input plane p + 1 - R
+        // (loaded in iteration p + 1 - R) and stage A's output plane p + 1 - 2R
+        // (computed in iteration p + 1 - R)
+        put(ic<0>{}, ic<WS>{}, in[slot<L>(M, R - 1)]);
+        if (FAST || act1) put(ic<1>{}, ic<WS>{}, mid[slot<L>(M, 2 * R - 1)]);
+
+        auto stA = [&]() __attribute__((always_inline)) {
+            T S[NXP];
+            stencil(fetch(ic<0>{}, ic<RS>{}), in, ic<SA>{}, wA, S);
+#pragma unroll
+            for (int ix = 0; ix < NXP; ++ix) {
+                if constexpr (HALF == 0) {
+                    const T u = in[SA][ix];
+                    mid[SA][ix] = fmaT(cA, S[ix], u);
+                    acc[SA][ix] = fmaT(bA, S[ix], u);
+                } else {
+                    mid[SA][ix] = fmaT(cA, S[ix], pu[(M + 1) & 1][ix]);
+                    acc[SA][ix] = fmaT(bA, S[ix], pa[(M + 1) & 1][ix]);
+                }
+            }
+        };
+        auto stB = [&](int q) __attribute__((always_inline)) {
+            T S[NXP];
+            stencil(fetch(ic<1>{}, ic<RS>{}), mid, ic<SB>{}, wB, S);
+            if (rowout && q < zend) {
+                const size_t off = (size_t)q * nxy + rowoff;
+                if constexpr (HALF == 0) {
+                    Vec<T, NXP> vy, va;
+#pragma unroll
+                    for (int ix = 0; ix < NXP; ++ix) {
+                        vy.v[ix] = fmaT(cB, S[ix], in[SB][ix]);
+                        va.v[ix] = fmaT(bB, S[ix], acc[SB][ix]);
+                    }
+                    gst<Vec<T, NXP>>(scr_y + off, vy);
+                    gst<Vec<T, NXP>>(scr_a + off, va);
+                } else {
+                    Vec<T, NXP> v;
+#pragma unroll
+                    for (int ix = 0; ix < NXP; ++ix) v.v[ix] = fmaT(bB, S[ix], acc[SB][ix]);
+                    gst_nt<Vec<T, NXP>>(dst + off, v);
+                }
+            }
+        };
+        const int q = p - 2 * R;
+        if constexpr (FAST) {
+            stA();
+            stB(q);
+        } else {
+            if (act1 && p >= z0) stA();               // stage A at plane p - R >= z0 - R
+            if (act2 && p >= z0 + 2 * R) stB(q);      // stage B at plane p - 2R >= z0
+        }
+    };
+
+    const int pstart = z0 - H;
+    const int niter = (zend - z0) + 2 * H;
+#pragma unroll
+    for (int d = 0; d < PD; ++d) load_plane(in_src, pstart + d, pin[d]);
+    auto trip = [&](int pb, auto FASTc) __attribute__((always_inline)) {
+        [&]<int... Ms>(std::integer_sequence<int, Ms...>) {
+            (body(ic<Ms>{}, FASTc, pstart + pb + Ms), ...);
+        }(std::make_integer_sequence<int, L>{});
+    };
+    // stage B starts at iteration 2H (p = z0 + 2R); trips from iteration 2L on
+    // have both stages active for the wavefronts that compute both
+    if (act2) {
+        int pb = 0;
+        for (; pb < niter && pb < 2 * L; pb += L) trip(pb, std::false_type{});
+        for (; pb < niter; pb += L) trip(pb, std::true_type{});
+    } else {
+        for (int pb = 0; pb < niter; pb += L) trip(pb, std::false_type{});
+    }
+}
+
+// ---------------------------------------------------------------------------
 // Fused RK4 step for stencils of radius R with one barrier per z plane.
 // Stage s evaluates plane p - sR in iteration p.  Each of the four stage
 // inputs has two LDS slots, chosen by iteration parity; in iteration p input
@@ -2275,6 +2507,26 @@ void fine_launch_1r(const ItemDesc *items, int nitems, int nblocks, int jstep, h
 #define FINE_1R(T, DT, R, NXP, NY, BXT, BY, PD, NAME)                                                    \
     FineEntry{VariantInfo{NAME, DT, 2 * R, BXT * NXP - 8 * R, BY * NY - 8 * R, NXP, BXT * BY, 1},       \
               &fine_launch_1r<T, R, NXP, NY, BXT, BY, PD>}
+// Two launches per step (stages 1-2, then 3-4) through the item's scratch
+// fields; the occupancy is that of the fuller half.
+template <typename T, int R, int NXP, int NW, int PD>
+void fine_launch_half_rows(const ItemDesc *items, int nitems, int nblocks, int jstep, hipStream_t s, int *occ)
+{
+    if (occ) {
+        int a = 1, b = 1;
+        occupancy_of((rk4_half_rows<T, R, NXP, NW, PD, 0>), 64 * NW, &a);
+        occupancy_of((rk4_half_rows<T, R, NXP, NW, PD, 1>), 64 * NW, &b);
+        *occ = a < b ? a : b;
+        return;
+    }
+    hipLaunchKernelGGL((rk4_half_rows<T, R, NXP, NW, PD, 0>), dim3(nblocks), dim3(64 * NW), 0, s, items, nitems,
+                       jstep);
+    hipLaunchKernelGGL((rk4_half_rows<T, R, NXP, NW, PD, 1>), dim3(nblocks), dim3(64 * NW), 0, s, items, nitems,
+                       jstep);
+}
+#define FINE_HALF_ROWS(T, DT, R, NXP, NW, PD, NAME)                                                      \
+    FineEntry{VariantInfo{NAME, DT, 2 * R, 64 * NXP, NW - 4 * R, NXP, 64 * NW, 1, 64 * NXP, 2},        \
+              &fine_launch_half_rows<T, R, NXP, NW, PD>}
 #define FINE_1C(T, DT, NXP, NY, BXT, BY, PD, PAD, NAME)                                                  \
     FineEntry{VariantInfo{NAME, DT, 2, BXT * NXP - 8, BY * NY - 8, NXP, BXT * BY, 1},                  \
               &fine_launch_1c<T, NXP, NY, BXT, BY, PD, PAD>}
@@ -2354,6 +2606,9 @@ const FineEntry kFine[] = {
     FINE_ROWS(float, 1, 1, 2, 12, 2, "rk4w_f32_x64_y16_p1x2_w12"),
     FINE_ROWS(float, 1, 1, 2, 16, 2, "rk4w_f32_x64_y24_p1x2_w16"),
     FINE_ROWS(double, 2, 1, 2, 12, 2, "rk4w_f64_x64_y16_p1x2_w12"),
+    FINE_HALF_ROWS(double, 2, 2, 2, 16, 2, "rk4h_f64_o4_x128_y8_p2_w16"),
+    FINE_HALF_ROWS(double, 2, 2, 2, 16, 1, "rk4h_f64_o4_x128_y8_p2_w16_d1"),
+    FINE_HALF_ROWS(float, 1, 2, 2, 16, 2, "rk4h_f32_o4_x128_y8_p2_w16"),
 };
 
 const CoarseEntry kCoarse[] = {

@@ -134,18 +134,20 @@ def test_fine_variants_bitwise_identical(pr, dtype, order):
 
 
 @pytest.mark.parametrize("dtype", [1, 2])
-@pytest.mark.parametrize("n3", [(128, 52, 21), (64, 37, 19), (256, 20, 9), (128, 8, 5)])
-def test_fine_whole_row_variants_bitwise_identical(pr, dtype, n3):
-    """The whole-row kernels (x neighbours across the wavefront) agree bit for
-    bit with the unfused reference and the tiled kernels, on grids with a
-    ragged last y tile, fewer rows than one tile and z shorter than the
-    pipeline."""
+@pytest.mark.parametrize("n3,order", [((128, 52, 21), 2), ((64, 37, 19), 2), ((256, 20, 9), 2), ((128, 8, 5), 2),
+                                      ((128, 52, 21), 4), ((128, 8, 5), 4), ((128, 19, 40), 4)])
+def test_fine_whole_row_variants_bitwise_identical(pr, dtype, n3, order):
+    """The whole-row kernels (x neighbours across the wavefront; for order 4
+    two launches of two stages each) agree bit for bit with the unfused
+    reference and the tiled kernels, on grids with a ragged last y tile,
+    fewer rows than one tile and z shorter than the pipeline."""
     import torch
     tdt = torch.float64 if dtype == 2 else torch.float32
-    p = W.small_problem(n=n3, a=(0.7, -0.45, 0.3), nu0=0.002, P=2, nf=64)
+    p = W.small_problem(n=n3, a=(0.7, -0.45, 0.3), nu0=0.002, P=2, nf=64, order=order)
     u = cuda(W.random_field(p.n, 141), tdt)
-    vs = _applicable(pr, 0, dtype, 2, p.n[0])
-    rows = [v["index"] for v in pr.variants(0) if v["nx_exact"] == p.n[0] and v["dtype"] == dtype]
+    vs = _applicable(pr, 0, dtype, order, p.n[0])
+    rows = [v["index"] for v in pr.variants(0)
+            if v["nx_exact"] == p.n[0] and v["dtype"] == dtype and v["order"] == order]
     if not rows:
         pytest.skip("no whole-row variant for n_x=%d" % p.n[0])
     outs = {}
@@ -283,6 +285,25 @@ def test_parareal_every_iterate_against_oracle(pr, orc):
         uT, _, states, _ = _solve(pr, [p], [u0], pr.PR_MODE_FP64)
         for n in range(p.P + 1):
             assert rel_l2(states[0][n], hist[K, n]) <= FP64_TOL, (K, n)
+
+
+@pytest.mark.parametrize("n3", [(128, 12, 10), (26, 18, 15)])
+def test_parareal_fourth_order_every_iterate_against_oracle(pr, orc, n3):
+    """The paper's fourth-order F inside Parareal, K = 0..P, every slice state
+    element by element against the oracle: on a 128-wide grid (whole-row
+    kernels, two launches per RK4 step) and on an odd grid (tiled kernel)."""
+    p = W.small_problem(n=n3, a=(0.6, 0.9, -0.4), nu0=0.0005, P=3, nf=12, nc=6, order=4)
+    u0 = W.random_field(p.n, 181)
+    _, _, hist = orc.parareal(p, u0, K=p.P, history=True)
+    for K in range(p.P + 1):
+        say("parareal order 4", n3, "K", K)
+        p.K = K
+        uT, _, states, _ = _solve(pr, [p], [u0], pr.PR_MODE_FP64)
+        for n in range(p.P + 1):
+            assert rel_l2(states[0][n], hist[K, n]) <= FP64_TOL, (K, n)
+    plan = pr.Plan([p], pr.PR_MODE_FP64)
+    fv = plan.kernel_variants()[0]
+    assert fv.startswith("rk4h_f64_o4") if n3[0] == 128 else fv.startswith("rk4_f64_o4"), fv
 
 
 def test_parareal_modes_bitwise_identical(pr):
