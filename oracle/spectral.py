@@ -169,6 +169,17 @@ def synth(n, q, coef):
     return out.real.copy()
 
 
+def synth_fft(n, q, coef):
+    """The field of synth(n, q, coef), evaluated with one inverse FFT: the
+    coefficients are summed into the DFT bins (q mod n) of the grid, which is
+    the same trigonometric sum sampled at x_i = i/n (exact up to rounding)."""
+    nx, ny, nz = (int(v) for v in n)
+    spec = np.zeros((nz, ny, nx), dtype=np.complex128)
+    q = np.asarray(q, dtype=np.int64)
+    np.add.at(spec, (q[:, 2] % nz, q[:, 1] % ny, q[:, 0] % nx), np.asarray(coef, dtype=np.complex128))
+    return (np.fft.ifftn(spec) * (nx * ny * nz)).real.copy()
+
+
 def synth_points(n, q, coef, flat_idx):
     """Values of sum_q coef_q e_q at the flat grid indices (z*ny + y)*nx + x."""
     nx, ny, nz = (int(v) for v in n)
@@ -203,6 +214,9 @@ class ModalSolution:
 
     def iterate_points(self, k, s, idx):
         return synth_points(self.p.n, self.q, self.c * self.Z[k, s], idx)
+
+    def iterate_fft(self, k, s):
+        return synth_fft(self.p.n, self.q, self.c * self.Z[k, s])
 
     def serial_fine(self, s=None):
         s = self.p.P if s is None else s

@@ -168,3 +168,22 @@ def test_thread_count_does_not_change_results(orc):
     finally:
         orc.set_threads(default)
     assert np.array_equal(U1, U4) and np.array_equal(log1, log4)
+
+
+def test_fft_synthesis_equals_direct_sum():
+    """The inverse-FFT evaluation of a trigonometric sum on the grid equals
+    the direct sum of its exponentials (wavenumbers of both signs, beyond the
+    Nyquist index, and repeated), and the synthesis of the initial modes
+    equals the initial field sampled in real arithmetic."""
+    rng = np.random.default_rng(5)
+    n = (12, 10, 9)
+    q = rng.integers(-20, 21, size=(40, 3))
+    q[5] = q[4]
+    c = rng.standard_normal(40) + 1j * rng.standard_normal(40)
+    assert np.allclose(S.synth_fft(n, q, c), S.synth(n, q, c), rtol=0, atol=1e-12)
+    p, modes = W.config("c1_32_fp64")
+    qq, cc = S.expand_modes(modes)
+    u0 = W.synth_u0(p.n, modes)
+    assert np.max(np.abs(S.synth_fft(p.n, qq, cc) - u0)) <= 1e-13 * np.max(np.abs(u0))
+    ms = S.ModalSolution(p, modes)
+    assert np.max(np.abs(ms.iterate_fft(p.K, p.P) - ms.iterate(p.K, p.P))) <= 1e-13
