@@ -342,6 +342,25 @@ int pr_autotune(const pr_problem *prob, int32_t dtype, int32_t batch, int32_t wh
 int pr_plan_autotune(pr_plan *plan, void *stream, int32_t *fine_variant, int32_t *fine_blocks_per_cu,
                      int32_t *coarse_variant, int32_t *coarse_blocks_per_cu);
 
+/*
+ * Persisted autotune table.  The choices of pr_autotune and pr_plan_autotune
+ * are kept per (device architecture, F or G, grid, dtype, fine order, batch)
+ * with the variant stored by name; plan creation and sweeps look them up for
+ * the current device's architecture only.
+ *   pr_autotune_save   write the table as JSON to `path` (HOST string)
+ *   pr_autotune_load   merge the entries of such a file into the table;
+ *                      entries naming a variant this build lacks are skipped;
+ *                      *loaded (HOST, may be NULL) receives the number merged
+ *   pr_autotune_clear  empty the table
+ * If the environment variable PR_AUTOTUNE_CACHE names a file, that file is
+ * loaded before the first lookup and rewritten after every tuning call.
+ * Errors: PR_EINVAL for a NULL path, an unreadable or unwritable file, or a
+ * file that is not such a table.  No device work.
+ */
+int pr_autotune_save(const char *path);
+int pr_autotune_load(const char *path, int32_t *loaded);
+int pr_autotune_clear(void);
+
 #ifdef __cplusplus
 }
 #endif

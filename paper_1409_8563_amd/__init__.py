@@ -10,6 +10,7 @@ The functions raise ImportError if the library was not built and
 from __future__ import annotations
 
 import ctypes
+import os
 
 from . import _lib as L
 from ._lib import (PR_ALLOW_UNSTABLE, PR_COARSEN_G, PR_CUBIC_INTERP, PR_EARLY_STOP, PR_FP32,  # noqa: F401
@@ -247,6 +248,22 @@ def copy_probe(src, dst, variant=0, blocks_per_cu=0, stream=None):
     check(lib().pr_copy_probe(_ptr(src, "src"), _ptr(dst, "dst", like=src), nb, int(variant), int(blocks_per_cu),
                               _stream_ptr(stream)))
     return dst
+
+
+def autotune_save(path):
+    """Write the library's tuned-kernel table as JSON to `path`."""
+    check(lib().pr_autotune_save(os.fsencode(path)))
+
+
+def autotune_load(path):
+    """Merge a saved tuned-kernel table; returns the number of entries merged."""
+    n = ctypes.c_int32(0)
+    check(lib().pr_autotune_load(os.fsencode(path), ctypes.byref(n)))
+    return n.value
+
+
+def autotune_clear():
+    check(lib().pr_autotune_clear())
 
 
 def check_stability(prob):

@@ -26,7 +26,8 @@ EXPORTS = ["pr_last_error", "pr_version", "pr_check_stability", "pr_fine_sweep",
            "pr_kernel_variant_count", "pr_kernel_variant_name", "pr_kernel_variant_info",
            "pr_autotune_workspace_bytes", "pr_autotune", "pr_plan_autotune", "pr_transfer_workspace_bytes",
            "pr_restrict", "pr_prolong", "pr_sweep_kernel_variant", "pr_defect_norm_static",
-           "pr_defect_static_scratch_bytes", "pr_copy_probe"]
+           "pr_defect_static_scratch_bytes", "pr_copy_probe", "pr_autotune_save", "pr_autotune_load",
+           "pr_autotune_clear"]
 
 
 class PrError(RuntimeError):
@@ -77,6 +78,9 @@ def lib():
     L.pr_defect_static_scratch_bytes.argtypes = []
     L.pr_defect_static_scratch_bytes.restype = _sz
     L.pr_copy_probe.argtypes = [_vp, _vp, _sz, _i32, _i32, _vp]
+    L.pr_autotune_save.argtypes = [ctypes.c_char_p]
+    L.pr_autotune_load.argtypes = [ctypes.c_char_p, ctypes.POINTER(_i32)]
+    L.pr_autotune_clear.argtypes = []
     L.pr_plan_workspace_bytes.argtypes = [pp, _i32, _i32]
     L.pr_plan_workspace_bytes.restype = _sz
     L.pr_plan_create.argtypes = [pp, _i32, _i32, _vp, _sz, ctypes.POINTER(_vp)]

@@ -57,24 +57,71 @@ struct Choice {
     int bpc = 0;
 };
 std::mutex g_tune_mu;
-// (which, nx, ny, nz, dtype, order, batch) -> choice of the tuner
-std::map<std::tuple<int, int, int, int, int, int, int>, Choice> g_tuned;
+// (arch, which, nx, ny, nz, dtype, order, batch) -> choice of the tuner
+using TuneKey = std::tuple<std::string, int, int, int, int, int, int, int>;
+std::map<TuneKey, Choice> g_tuned;
+bool g_cache_loaded = false;   // the PR_AUTOTUNE_CACHE file was read
+
+// Architecture name of the current device ("gfx950"), or "none" without a
+// device: tuned choices apply only on the architecture they were timed on.
+const std::string &current_arch()
+{
+    static std::string arch;
+    static std::once_flag once;
+    std::call_once(once, [] {
+        int n = 0, dev = 0;
+        hipDeviceProp_t prop;
+        if (hipGetDeviceCount(&n) == hipSuccess && n > 0 && hipGetDevice(&dev) == hipSuccess &&
+            hipGetDeviceProperties(&prop, dev) == hipSuccess) {
+            arch = prop.gcnArchName;
+            const size_t c = arch.find(':');
+            if (c != std::string::npos) arch.resize(c);
+        }
+        if (arch.empty()) arch = "none";
+    });
+    return arch;
+}
+
+int load_tune_cache_locked(const char *path, int *loaded);
+
+// Read the file named by PR_AUTOTUNE_CACHE once, before the first lookup.
+void autoload_tune_cache_locked()
+{
+    if (g_cache_loaded) return;
+    g_cache_loaded = true;
+    const char *path = std::getenv("PR_AUTOTUNE_CACHE");
+    if (path && *path) {
+        int n = 0;
+        (void)load_tune_cache_locked(path, &n);
+    }
+}
 
 // Tuned choice for a shape: the entry of this batch, else any batch of the shape.
 bool tuned_choice(int which, const pr_problem &p, int dtype, int order, int batch, Choice *c)
 {
+    const std::string &arch = current_arch();
     std::lock_guard<std::mutex> lk(g_tune_mu);
-    auto it = g_tuned.find({which, p.n[0], p.n[1], p.n[2], dtype, order, batch});
+    autoload_tune_cache_locked();
+    auto it = g_tuned.find({arch, which, p.n[0], p.n[1], p.n[2], dtype, order, batch});
     if (it == g_tuned.end()) {
-        it = g_tuned.lower_bound({which, p.n[0], p.n[1], p.n[2], dtype, order, 0});
+        it = g_tuned.lower_bound({arch, which, p.n[0], p.n[1], p.n[2], dtype, order, 0});
         if (it == g_tuned.end()) return false;
         const auto &k = it->first;
-        if (std::get<0>(k) != which || std::get<1>(k) != p.n[0] || std::get<2>(k) != p.n[1] ||
-            std::get<3>(k) != p.n[2] || std::get<4>(k) != dtype || std::get<5>(k) != order)
+        if (std::get<0>(k) != arch || std::get<1>(k) != which || std::get<2>(k) != p.n[0] ||
+            std::get<3>(k) != p.n[1] || std::get<4>(k) != p.n[2] || std::get<5>(k) != dtype ||
+            std::get<6>(k) != order)
             return false;
     }
     *c = it->second;
     return true;
+}
+
+void record_tuned(int which, const pr_problem &p, int dtype, int order, int batch, Choice c)
+{
+    const std::string &arch = current_arch();
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    autoload_tune_cache_locked();
+    g_tuned[{arch, which, p.n[0], p.n[1], p.n[2], dtype, order, batch}] = c;
 }
 
 int g_num_cus = 0;
@@ -258,6 +305,134 @@ int find_coarse(const char *name)
     for (int v = 2; v < pr::coarse_variant_count(); ++v)
         if (!std::strcmp(pr::coarse_variant(v)->name, name)) return v;
     return -1;
+}
+
+// ---- persisted autotune table ---------------------------------------------
+//
+// JSON written and read by the library only:
+//   {"format": "pr-autotune-1", "entries": [
+//     {"arch": "gfx950", "which": 0, "n": [128, 128, 128], "dtype": 2, "order": 2,
+//      "batch": 16, "variant": "rk4w_f64_x128_y8_p2x1_w16", "blocks_per_cu": 0}, ...]}
+// Variants are stored by name; entries naming a variant this build does not
+// have are skipped when loading.
+
+bool json_field(const std::string &obj, const char *key, size_t *pos)
+{
+    const std::string k = std::string("\"") + key + "\"";
+    size_t i = obj.find(k);
+    if (i == std::string::npos) return false;
+    i = obj.find(':', i + k.size());
+    if (i == std::string::npos) return false;
+    *pos = i + 1;
+    return true;
+}
+bool json_int(const std::string &obj, const char *key, int *out)
+{
+    size_t i;
+    if (!json_field(obj, key, &i)) return false;
+    char *end = nullptr;
+    const long v = std::strtol(obj.c_str() + i, &end, 10);
+    if (end == obj.c_str() + i) return false;
+    *out = (int)v;
+    return true;
+}
+bool json_str(const std::string &obj, const char *key, std::string *out)
+{
+    size_t i;
+    if (!json_field(obj, key, &i)) return false;
+    const size_t a = obj.find('"', i);
+    if (a == std::string::npos) return false;
+    const size_t b = obj.find('"', a + 1);
+    if (b == std::string::npos) return false;
+    *out = obj.substr(a + 1, b - a - 1);
+    return true;
+}
+bool json_int3(const std::string &obj, const char *key, int out[3])
+{
+    size_t i;
+    if (!json_field(obj, key, &i)) return false;
+    i = obj.find('[', i);
+    if (i == std::string::npos) return false;
+    const char *c = obj.c_str() + i + 1;
+    for (int d = 0; d < 3; ++d) {
+        char *end = nullptr;
+        out[d] = (int)std::strtol(c, &end, 10);
+        if (end == c) return false;
+        c = end;
+        while (*c == ' ' || *c == ',') ++c;
+    }
+    return true;
+}
+
+int load_tune_cache_locked(const char *path, int *loaded)
+{
+    *loaded = 0;
+    FILE *f = std::fopen(path, "rb");
+    if (!f) return fail(PR_EINVAL, "cannot open autotune cache %s", path);
+    std::string txt;
+    char buf[4096];
+    size_t got;
+    while ((got = std::fread(buf, 1, sizeof buf, f)) > 0) txt.append(buf, got);
+    std::fclose(f);
+    if (txt.find("\"pr-autotune-1\"") == std::string::npos)
+        return fail(PR_EINVAL, "%s is not an autotune cache of this library", path);
+    size_t i = txt.find("\"entries\"");
+    if (i == std::string::npos) return fail(PR_EINVAL, "%s has no entries list", path);
+    while ((i = txt.find('{', i)) != std::string::npos) {
+        const size_t j = txt.find('}', i);
+        if (j == std::string::npos) break;
+        const std::string obj = txt.substr(i, j - i + 1);
+        i = j + 1;
+        std::string arch, name;
+        int which, n[3], dtype, order, batch, bpc;
+        if (!json_str(obj, "arch", &arch) || !json_int(obj, "which", &which) || !json_int3(obj, "n", n) ||
+            !json_int(obj, "dtype", &dtype) || !json_int(obj, "order", &order) || !json_int(obj, "batch", &batch) ||
+            !json_str(obj, "variant", &name) || !json_int(obj, "blocks_per_cu", &bpc))
+            continue;
+        if ((which != 0 && which != 1) || bpc < 0 || bpc > 64) continue;
+        const int v = which == 0 ? find_fine(name.c_str()) : find_coarse(name.c_str());
+        if (v < 2) continue;
+        g_tuned[{arch, which, n[0], n[1], n[2], dtype, order, batch}] = Choice{v, bpc};
+        ++*loaded;
+    }
+    return PR_OK;
+}
+
+int save_tune_cache_locked(const char *path)
+{
+    std::string out = "{\"format\": \"pr-autotune-1\", \"entries\": [";
+    bool first = true;
+    for (const auto &e : g_tuned) {
+        const auto &k = e.first;
+        const int which = std::get<1>(k), v = e.second.v;
+        const VariantInfo *vi = which == 0 ? pr::fine_variant(v) : pr::coarse_variant(v);
+        if (!vi) continue;
+        char line[512];
+        std::snprintf(line, sizeof line,
+                      "%s\n  {\"arch\": \"%s\", \"which\": %d, \"n\": [%d, %d, %d], \"dtype\": %d, "
+                      "\"order\": %d, \"batch\": %d, \"variant\": \"%s\", \"blocks_per_cu\": %d}",
+                      first ? "" : ",", std::get<0>(k).c_str(), which, std::get<2>(k), std::get<3>(k),
+                      std::get<4>(k), std::get<5>(k), std::get<6>(k), std::get<7>(k), vi->name, e.second.bpc);
+        out += line;
+        first = false;
+    }
+    out += "\n]}\n";
+    const std::string tmp = std::string(path) + ".tmp";
+    FILE *f = std::fopen(tmp.c_str(), "wb");
+    if (!f) return fail(PR_EINVAL, "cannot write autotune cache %s", tmp.c_str());
+    const bool ok = std::fwrite(out.data(), 1, out.size(), f) == out.size();
+    if (std::fclose(f) != 0 || !ok || std::rename(tmp.c_str(), path) != 0)
+        return fail(PR_EINVAL, "cannot write autotune cache %s", path);
+    return PR_OK;
+}
+
+// After tuning: write the table to the file named by PR_AUTOTUNE_CACHE.
+void save_tune_cache_env()
+{
+    const char *path = std::getenv("PR_AUTOTUNE_CACHE");
+    if (!path || !*path) return;
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    (void)save_tune_cache_locked(path);
 }
 
 bool fine_applicable(int v, int dtype, int order, const pr_problem &p)
@@ -1740,6 +1915,33 @@ size_t pr_autotune_workspace_bytes(const pr_problem *prob, int32_t dtype, int32_
     return 2 * align256(states) + sweep_ws(*prob, dtype, batch, false);
 }
 
+int pr_autotune_save(const char *path)
+{
+    if (!path || !*path) return fail(PR_EINVAL, "path is NULL or empty");
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    autoload_tune_cache_locked();
+    return save_tune_cache_locked(path);
+}
+
+int pr_autotune_load(const char *path, int32_t *loaded)
+{
+    if (!path || !*path) return fail(PR_EINVAL, "path is NULL or empty");
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    autoload_tune_cache_locked();
+    int n = 0;
+    const int rc = load_tune_cache_locked(path, &n);
+    if (loaded) *loaded = n;
+    return rc;
+}
+
+int pr_autotune_clear(void)
+{
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    g_tuned.clear();
+    g_cache_loaded = true;   // an explicit clear also drops the environment's cache
+    return PR_OK;
+}
+
 int pr_autotune(const pr_problem *prob, int32_t dtype, int32_t batch, int32_t which, void *ws, size_t ws_bytes,
                 void *stream, int32_t *best_variant)
 {
@@ -1801,10 +2003,8 @@ int pr_autotune(const pr_problem *prob, int32_t dtype, int32_t batch, int32_t wh
     (void)hipEventDestroy(e1);
     if (rc) return rc;
     if (bestc.v < 2) return fail(PR_EUNSUPPORTED, "no fused variant applies");
-    {
-        std::lock_guard<std::mutex> lk(g_tune_mu);
-        g_tuned[{which, p.n[0], p.n[1], p.n[2], dtype, which == 0 ? p.fine_order : 0, batch}] = bestc;
-    }
+    record_tuned(which, p, dtype, which == 0 ? p.fine_order : 0, batch, bestc);
+    save_tune_cache_env();
     if (best_variant) *best_variant = bestc.v;
     return PR_OK;
 }
@@ -1920,6 +2120,23 @@ int pr_plan_autotune(pr_plan *pl, void *stream, int32_t *fine_variant, int32_t *
         }
         pl->coarse_v = saved_g.v;
         pl->coarse_bpc = saved_g.bpc;
+    }
+    if (!rc) {
+        // remember the choices under the keys plan creation looks up: per
+        // grid of a group, the batch of all slices of the instances with that
+        // grid; G at the first instance's (coarse) grid and the instance count
+        for (int g = 0; g < ngrp; ++g)
+            for (int i : pl->fgroups[g].insts) {
+                const pr_problem &pi = pl->probs[i];
+                int batch = 0;
+                for (int j = 0; j < pl->ninst; ++j)
+                    if (pl->probs[j].n[0] == pi.n[0] && pl->probs[j].n[1] == pi.n[1] &&
+                        pl->probs[j].n[2] == pi.n[2])
+                        batch += pl->probs[j].P;
+                record_tuned(0, pi, pl->dtype, pi.fine_order, batch, Choice{pl->fgroups[g].v, pl->fgroups[g].bpc});
+            }
+        record_tuned(1, coarse_grid(pl->probs[0]), pl->dtype, 0, pl->ninst, Choice{pl->coarse_v, pl->coarse_bpc});
+        save_tune_cache_env();
     }
     int r2 = build_tables(pl);
     if (!rc) rc = r2;

@@ -675,225 +675,6 @@ __global__ void __launch_bounds__(BXT *BY)
 }
 
 // ---------------------------------------------------------------------------
-template <typename T, int NXP, int NY, int BXT, int BY, int PD, int PAD>
-__global__ void __launch_bounds__(BXT *BY)
-    rk4_step_fused1c(const ItemDesc *__restrict__ items, int nitems, int jstep)
-{
-    static_assert(4 % PD == 0, "prefetch depth must divide the unroll");
-    constexpr int R = 1;
-    constexpr int H = 4;
-    constexpr int EX = BXT * NXP, EY = BY * NY;
-    constexpr int TX = EX - 2 * H, TY = EY - 2 * H;
-    constexpr int L = 4;                                   // z-ring length (even: LDS slot = phase parity)
-    constexpr int CO = NXP;                                // halo columns in LDS, one aligned group
-    constexpr int LX = EX + 2 * CO + PAD;
-    constexpr int LY = EY + 2;
-    static_assert(TX > 0 && TY > 0, "tile too small for the halo");
-    static_assert(PAD % NXP == 0, "padding must keep vector alignment");
-    // the two slots are separate arrays so that the compiler can move this
-    // iteration's LDS reads above this iteration's LDS writes
-    __shared__ __align__(16) T ldsA[4][LY][LX];
-    __shared__ __align__(16) T ldsB[4][LY][LX];
-
-    const int lb = xcd_remap((int)blockIdx.x, (int)gridDim.x);
-    const ItemDesc &it = items[find_item(items, nitems, lb)];
-    if (jstep >= it.nsteps) return;
-    const int local = lb - it.block_begin;
-    if (local < 0 || local >= it.nblocks) return;
-
-    const int nx = it.nx, ny = it.ny, nz = it.nz;
-    const int txt = local % it.tiles_x;
-    const int rest = local / it.tiles_x;
-    const int tyt = rest % it.tiles_y;
-    const int zc = rest / it.tiles_y;
-    const int x0 = txt * TX, y0 = tyt * TY;
-    const int z0 = zc * it.tz;
-    const int zend = min(z0 + it.tz, nz);
-
-    const T *src;
-    T *dst;
-    pingpong<T>(it, jstep, it.nsteps, src, dst);
-
-    const int tid = (int)threadIdx.x;
-    const int txi = tid % BXT, tyi = tid / BXT;
-    const int cx0 = txi * NXP, ry0 = tyi * NY;
-    const int gx0 = wrapi(x0 - H + cx0, nx);
-    int rowoff[NY];
-    bool yok[NY];
-#pragma unroll
-    for (int iy = 0; iy < NY; ++iy) {
-        const int ry = ry0 + iy;
-        rowoff[iy] = wrapi(y0 - H + ry, ny) * nx + gx0;
-        yok[iy] = (ry >= H) && (ry < H + TY) && (y0 + ry - H < ny);
-    }
-    const bool xok = (cx0 >= H) && (cx0 < H + TX) && (x0 + cx0 - H < nx);
-    const int nxy = nx * ny;
-
-    const double dt = it.dt;
-    const double t = (double)(it.step0 + jstep) * dt;
-    const double nu1 = nu_at(it, t);
-    const double nu2 = it.frozen ? nu1 : nu_at(it, t + 0.5 * dt);
-    const double nu4 = it.frozen ? nu1 : nu_at(it, t + dt);
-    const Wts<T, R> w1 = uni(fine_weights<T, R>(it, nu1));
-    const Wts<T, R> w2 = uni(fine_weights<T, R>(it, nu2));
-    const Wts<T, R> w4 = uni(fine_weights<T, R>(it, nu4));
-    RK4Consts<T> kc = rk4_consts<T>(dt);
-    kc.c1 = uni(kc.c1);
-    kc.c2 = uni(kc.c2);
-    kc.c3 = uni(kc.c3);
-    kc.b1 = uni(kc.b1);
-    kc.b2 = uni(kc.b2);
-    kc.b3 = uni(kc.b3);
-    kc.b4 = uni(kc.b4);
-
-    T ur[L][NY][NXP], y1[L][NY][NXP], y2[L][NY][NXP], y3[L][NY][NXP], ac[L][NY][NXP];
-    T pf[PD][NY][NXP];   // planes p .. p+PD-1 in flight (prefetch ring)
-
-    auto load_plane = [&](int p, T(&dstp)[NY][NXP]) {
-        const T *base = src + (size_t)wrapi(p, nz) * nxy;
-#pragma unroll
-        for (int iy = 0; iy < NY; ++iy) {
-            const Vec<T, NXP> v = gld<Vec<T, NXP>>(base + rowoff[iy]);
-#pragma unroll
-            for (int ix = 0; ix < NXP; ++ix) dstp[iy][ix] = v.v[ix];
-        }
-    };
-
-    // write this thread's values of a plane to LDS buffer B, slot SL
-    auto plane = [&](auto SLc, int b) -> T(*)[LX] {
-        if constexpr (decltype(SLc)::value == 0) return ldsA[b];
-        else return ldsB[b];
-    };
-    auto put = [&](auto Bc, auto SLc, const T(&v)[NY][NXP]) {
-        constexpr int B = decltype(Bc)::value;
-        T(*lp)[LX] = plane(SLc, B);
-#pragma unroll
-        for (int iy = 0; iy < NY; ++iy) {
-            Vec<T, NXP> w;
-#pragma unroll
-            for (int ix = 0; ix < NXP; ++ix) w.v[ix] = v[iy][ix];
-            *reinterpret_cast<Vec<T, NXP> *>(&lp[1 + ry0 + iy][CO + cx0]) = w;
-        }
-    };
-
-    // S = L(f)(plane q) for the thread's points.  Centre and z neighbours
-    // from the ring `in` (slots SC, SC_M = plane q-1, SC_P = plane q+1),
-    // in-plane neighbours from LDS buffer B, slot SL.
-    auto stencil = [&](auto Bc, auto SLc, const T(&in)[L][NY][NXP], auto SCc, auto SCMc, auto SCPc,
-                       const Wts<T, R> &w, T(&S)[NY][NXP]) {
-        constexpr int B = decltype(Bc)::value;
-        constexpr int SC = decltype(SCc)::value;
-        constexpr int SCM = decltype(SCMc)::value;
-        constexpr int SCP = decltype(SCPc)::value;
-        const T(*lp)[LX] = plane(SLc, B);
-        Vec<T, NXP> up, dn;
-        up = *reinterpret_cast<const Vec<T, NXP> *>(&lp[ry0][CO + cx0]);
-        dn = *reinterpret_cast<const Vec<T, NXP> *>(&lp[1 + ry0 + NY][CO + cx0]);
-#pragma unroll
-        for (int iy = 0; iy < NY; ++iy) {
-            const Vec<T, NXP> lf = *reinterpret_cast<const Vec<T, NXP> *>(&lp[1 + ry0 + iy][CO + cx0 - NXP]);
-            const Vec<T, NXP> rt = *reinterpret_cast<const Vec<T, NXP> *>(&lp[1 + ry0 + iy][CO + cx0 + NXP]);
-#pragma unroll
-            for (int ix = 0; ix < NXP; ++ix) {
-                T mn[3][1], pn[3][1];
-                mn[0][0] = (ix >= 1) ? in[SC][iy][ix - 1] : lf.v[NXP - 1];
-                pn[0][0] = (ix + 1 < NXP) ? in[SC][iy][ix + 1] : rt.v[0];
-                mn[1][0] = (iy >= 1) ? in[SC][iy - 1][ix] : up.v[ix];
-                pn[1][0] = (iy + 1 < NY) ? in[SC][iy + 1][ix] : dn.v[ix];
-                mn[2][0] = in[SCM][iy][ix];
-                pn[2][0] = in[SCP][iy][ix];
-                S[iy][ix] = apply<T, 1>(w, in[SC][iy][ix], mn, pn);
-            }
-        }
-    };
-
-    auto body = [&](auto Mc, int p) {
-        constexpr int M = decltype(Mc)::value;
-        constexpr int WS = M & 1;        // slot written in this iteration
-        constexpr int RS = (M + 1) & 1;  // slot written in the previous iteration
-        __syncthreads();
-#pragma unroll
-        for (int iy = 0; iy < NY; ++iy)
-#pragma unroll
-            for (int ix = 0; ix < NXP; ++ix) ur[slot<L>(M, 0)][iy][ix] = pf[M % PD][iy][ix];
-        load_plane(p + PD, pf[M % PD]);
-        put(ic<0>{}, ic<WS>{}, ur[slot<L>(M, 0)]);
-
-        T S[NY][NXP];
-        // All stages run in every iteration: during the pipeline fill they
-        // produce planes below the chunk that no stored output depends on,
-        // and branch-free iterations let the LDS reads be scheduled early.
-        // stage 1 at plane p - 1
-        {
-            stencil(ic<0>{}, ic<RS>{}, ur, ic<slot<L>(M, 1)>{}, ic<slot<L>(M, 2)>{}, ic<slot<L>(M, 0)>{}, w1, S);
-#pragma unroll
-            for (int iy = 0; iy < NY; ++iy)
-#pragma unroll
-                for (int ix = 0; ix < NXP; ++ix) {
-                    const T u = ur[slot<L>(M, 1)][iy][ix];
-                    y1[slot<L>(M, 1)][iy][ix] = fmaT(kc.c1, S[iy][ix], u);
-                    ac[slot<L>(M, 1)][iy][ix] = fmaT(kc.b1, S[iy][ix], u);
-                }
-            put(ic<1>{}, ic<WS>{}, y1[slot<L>(M, 1)]);
-        }
-        // stage 2 at plane p - 2
-        {
-            stencil(ic<1>{}, ic<RS>{}, y1, ic<slot<L>(M, 2)>{}, ic<slot<L>(M, 3)>{}, ic<slot<L>(M, 1)>{}, w2, S);
-#pragma unroll
-            for (int iy = 0; iy < NY; ++iy)
-#pragma unroll
-                for (int ix = 0; ix < NXP; ++ix) {
-                    const T u = ur[slot<L>(M, 2)][iy][ix];
-                    y2[slot<L>(M, 2)][iy][ix] = fmaT(kc.c2, S[iy][ix], u);
-                    ac[slot<L>(M, 2)][iy][ix] = fmaT(kc.b2, S[iy][ix], ac[slot<L>(M, 2)][iy][ix]);
-                }
-            put(ic<2>{}, ic<WS>{}, y2[slot<L>(M, 2)]);
-        }
-        // stage 3 at plane p - 3
-        {
-            stencil(ic<2>{}, ic<RS>{}, y2, ic<slot<L>(M, 3)>{}, ic<slot<L>(M, 4)>{}, ic<slot<L>(M, 2)>{}, w2, S);
-#pragma unroll
-            for (int iy = 0; iy < NY; ++iy)
-#pragma unroll
-                for (int ix = 0; ix < NXP; ++ix) {
-                    const T u = ur[slot<L>(M, 3)][iy][ix];
-                    y3[slot<L>(M, 3)][iy][ix] = fmaT(kc.c3, S[iy][ix], u);
-                    ac[slot<L>(M, 3)][iy][ix] = fmaT(kc.b3, S[iy][ix], ac[slot<L>(M, 3)][iy][ix]);
-                }
-            put(ic<3>{}, ic<WS>{}, y3[slot<L>(M, 3)]);
-        }
-        // stage 4 at plane p - 4, stored
-        const int q = p - 4;
-        stencil(ic<3>{}, ic<RS>{}, y3, ic<slot<L>(M, 4)>{}, ic<slot<L>(M, 5)>{}, ic<slot<L>(M, 3)>{}, w4, S);
-        if (q >= z0 && q < zend) {
-            if (xok) {
-                T *obase = dst + (size_t)q * nxy;
-#pragma unroll
-                for (int iy = 0; iy < NY; ++iy) {
-                    if (yok[iy]) {
-                        Vec<T, NXP> v;
-#pragma unroll
-                        for (int ix = 0; ix < NXP; ++ix)
-                            v.v[ix] = fmaT(kc.b4, S[iy][ix], ac[slot<L>(M, 4)][iy][ix]);
-                        gst<Vec<T, NXP>>(obase + rowoff[iy], v);
-                    }
-                }
-            }
-        }
-    };
-
-    const int pstart = z0 - 4;
-    const int niter = (zend - z0) + 8;
-#pragma unroll
-    for (int d = 0; d < PD; ++d) load_plane(pstart + d, pf[d]);
-    for (int pb = 0; pb < niter; pb += L) {
-        [&]<int... Ms>(std::integer_sequence<int, Ms...>) {
-            (body(ic<Ms>{}, pstart + pb + Ms), ...);
-        }(std::make_integer_sequence<int, L>{});
-    }
-}
-
-// ---------------------------------------------------------------------------
 // Fused RK4 step over whole x rows (radius-1 stencils, n_x = 64 * NXP).
 //
 // Lane l of a wavefront holds x = l*NXP .. l*NXP + NXP-1 of NY consecutive
@@ -1977,330 +1758,6 @@ __global__ void __launch_bounds__(64 * NW)
 }
 
 // ---------------------------------------------------------------------------
-template <typename T, int S, int NXP, int NY, int BXT, int BY, int PD>
-__global__ void __launch_bounds__(BXT *BY)
-    euler_chunk_fused1c(const ItemDesc *__restrict__ items, int nitems, int chunk)
-{
-    static_assert(6 % PD == 0, "prefetch depth must divide the unroll");
-    constexpr int H = S;
-    constexpr int EX = BXT * NXP, EY = BY * NY;
-    constexpr int TX = EX - 2 * H, TY = EY - 2 * H;
-    constexpr int L = 3;                                   // z-ring length
-    constexpr int U = 6;                                   // unroll: ring phase and LDS slot parity
-    constexpr int CO = NXP;
-    constexpr int LX = EX + 2 * CO + (sizeof(T) == 8 ? 2 : 4);
-    constexpr int LY = EY + 2;
-    static_assert(TX > 0 && TY > 0, "tile too small for the halo");
-    __shared__ __align__(16) T ldsA[S][LY][LX];
-    __shared__ __align__(16) T ldsB[S][LY][LX];
-
-    const int lb = xcd_remap((int)blockIdx.x, (int)gridDim.x);
-    const ItemDesc &it = items[find_item(items, nitems, lb)];
-    const int nchunks = (it.nsteps + S - 1) / S;
-    if (chunk >= nchunks) return;
-    const int local = lb - it.block_begin;
-    if (local < 0 || local >= it.nblocks) return;
-
-    const int nx = it.nx, ny = it.ny, nz = it.nz;
-    const int txt = local % it.tiles_x;
-    const int rest = local / it.tiles_x;
-    const int tyt = rest % it.tiles_y;
-    const int zc = rest / it.tiles_y;
-    const int x0 = txt * TX, y0 = tyt * TY;
-    const int z0 = zc * it.tz;
-    const int zend = min(z0 + it.tz, nz);
-
-    const T *src;
-    T *dst;
-    pingpong<T>(it, chunk, nchunks, src, dst);
-
-    const int tid = (int)threadIdx.x;
-    const int txi = tid % BXT, tyi = tid / BXT;
-    const int cx0 = txi * NXP, ry0 = tyi * NY;
-    const int gx0 = wrapi(x0 - H + cx0, nx);
-    int rowoff[NY];
-    bool yok[NY];
-#pragma unroll
-    for (int iy = 0; iy < NY; ++iy) {
-        const int ry = ry0 + iy;
-        rowoff[iy] = wrapi(y0 - H + ry, ny) * nx + gx0;
-        yok[iy] = (ry >= H) && (ry < H + TY) && (y0 + ry - H < ny);
-    }
-    const bool xok = (cx0 >= H) && (cx0 < H + TX) && (x0 + cx0 - H < nx);
-    const int nxy = nx * ny;
-
-    Wts<T, 1> w[S];
-    T dts[S];
-#pragma unroll
-    for (int s = 0; s < S; ++s) {
-        const int64_t j = (int64_t)chunk * S + s;
-        const bool act = j < it.nsteps;
-        const double nu = nu_at(it, (double)(it.step0 + j) * it.dt);
-        w[s] = uni(coarse_weights<T>(it, nu));
-        dts[s] = uni(act ? (T)it.dt : (T)0);
-    }
-
-    T f[S][L][NY][NXP];
-    T pf[PD][NY][NXP];
-
-    auto load_plane = [&](int p, T(&dstp)[NY][NXP]) {
-        const T *base = src + (size_t)wrapi(p, nz) * nxy;
-#pragma unroll
-        for (int iy = 0; iy < NY; ++iy) {
-            const Vec<T, NXP> v = gld<Vec<T, NXP>>(base + rowoff[iy]);
-#pragma unroll
-            for (int ix = 0; ix < NXP; ++ix) dstp[iy][ix] = v.v[ix];
-        }
-    };
-
-    auto body = [&](auto Mc, int p) {
-        constexpr int M = decltype(Mc)::value;
-        constexpr int WS = M & 1, RS = (M + 1) & 1;
-        __syncthreads();
-#pragma unroll
-        for (int iy = 0; iy < NY; ++iy) {
-            Vec<T, NXP> wv;
-#pragma unroll
-            for (int ix = 0; ix < NXP; ++ix) {
-                f[0][slot<L>(M, 0)][iy][ix] = pf[M % PD][iy][ix];
-                wv.v[ix] = pf[M % PD][iy][ix];
-            }
-            T(*lw)[LX] = WS == 0 ? ldsA[0] : ldsB[0];
-            *reinterpret_cast<Vec<T, NXP> *>(&lw[1 + ry0 + iy][CO + cx0]) = wv;
-        }
-        load_plane(p + PD, pf[M % PD]);
-
-        [&]<int... Ss>(std::integer_sequence<int, Ss...>) {
-            (
-                [&] {
-                    constexpr int s = Ss + 1;          // stage s computes plane p - s from f[s-1]
-                    constexpr int sc = slot<L>(M, s);
-                    // branch-free: fill iterations compute planes no stored output needs
-                    {
-                        const T(*lr)[LX] = RS == 0 ? ldsA[s - 1] : ldsB[s - 1];
-                        const Vec<T, NXP> up = *reinterpret_cast<const Vec<T, NXP> *>(&lr[ry0][CO + cx0]);
-                        const Vec<T, NXP> dn = *reinterpret_cast<const Vec<T, NXP> *>(&lr[1 + ry0 + NY][CO + cx0]);
-                        T res[NY][NXP];
-#pragma unroll
-                        for (int iy = 0; iy < NY; ++iy) {
-                            const Vec<T, NXP> lf = *reinterpret_cast<const Vec<T, NXP> *>(&lr[1 + ry0 + iy][CO + cx0 - NXP]);
-                            const Vec<T, NXP> rt = *reinterpret_cast<const Vec<T, NXP> *>(&lr[1 + ry0 + iy][CO + cx0 + NXP]);
-#pragma unroll
-                            for (int ix = 0; ix < NXP; ++ix) {
-                                T mn[3][1], pn[3][1];
-                                mn[0][0] = (ix >= 1) ? f[s - 1][sc][iy][ix - 1] : lf.v[NXP - 1];
-                                pn[0][0] = (ix + 1 < NXP) ? f[s - 1][sc][iy][ix + 1] : rt.v[0];
-                                mn[1][0] = (iy >= 1) ? f[s - 1][sc][iy - 1][ix] : up.v[ix];
-                                pn[1][0] = (iy + 1 < NY) ? f[s - 1][sc][iy + 1][ix] : dn.v[ix];
-                                mn[2][0] = f[s - 1][slot<L>(M, s + 1)][iy][ix];
-                                pn[2][0] = f[s - 1][slot<L>(M, s - 1)][iy][ix];
-                                const T cen = f[s - 1][sc][iy][ix];
-                                const T Sv = apply<T, 1>(w[s - 1], cen, mn, pn);
-                                res[iy][ix] = fmaT(dts[s - 1], Sv, cen);
-                            }
-                        }
-                        if constexpr (s < S) {
-#pragma unroll
-                            for (int iy = 0; iy < NY; ++iy) {
-                                Vec<T, NXP> wv;
-#pragma unroll
-                                for (int ix = 0; ix < NXP; ++ix) {
-                                    f[s][slot<L>(M, s)][iy][ix] = res[iy][ix];
-                                    wv.v[ix] = res[iy][ix];
-                                }
-                                T(*lw)[LX] = WS == 0 ? ldsA[s] : ldsB[s];
-                                *reinterpret_cast<Vec<T, NXP> *>(&lw[1 + ry0 + iy][CO + cx0]) = wv;
-                            }
-                        } else {
-                            const int q = p - S;
-                            if (xok && q >= z0 && q < zend) {
-                                T *obase = dst + (size_t)q * nxy;
-#pragma unroll
-                                for (int iy = 0; iy < NY; ++iy) {
-                                    if (yok[iy]) {
-                                        Vec<T, NXP> v;
-#pragma unroll
-                                        for (int ix = 0; ix < NXP; ++ix) v.v[ix] = res[iy][ix];
-                                        gst<Vec<T, NXP>>(obase + rowoff[iy], v);
-                                    }
-                                }
-                            }
-                        }
-                    }
-                }(),
-                ...);
-        }(std::make_integer_sequence<int, S>{});
-    };
-
-    const int pstart = z0 - S;
-    const int niter = (zend - z0) + 2 * S;
-#pragma unroll
-    for (int d = 0; d < PD; ++d) load_plane(pstart + d, pf[d]);
-    for (int pb = 0; pb < niter; pb += U) {
-        [&]<int... Ms>(std::integer_sequence<int, Ms...>) {
-            (body(ic<Ms>{}, pstart + pb + Ms), ...);
-        }(std::make_integer_sequence<int, U>{});
-    }
-}
-
-// ---------------------------------------------------------------------------
-// Fused forward Euler chunk: S steps of Algorithm 2 per HBM pass.  Steps past
-// the end of a field's sweep are exact identities (zero step size).
-// ---------------------------------------------------------------------------
-template <typename T, int S, int NXP, int NY, int BXT, int BY>
-__global__ void __launch_bounds__(BXT *BY)
-    euler_chunk_fused(const ItemDesc *__restrict__ items, int nitems, int chunk)
-{
-    constexpr int R = 1;
-    constexpr int H = S;
-    constexpr int EX = BXT * NXP, EY = BY * NY;
-    constexpr int TX = EX - 2 * H, TY = EY - 2 * H;
-    constexpr int L = 3;
-    constexpr int CO = ((R + NXP - 1) / NXP) * NXP;
-    constexpr int LX = EX + 2 * CO + (sizeof(T) == 8 ? 2 : 4);
-    constexpr int LY = EY + 2 * R;
-    static_assert(TX > 0 && TY > 0, "tile too small for the halo");
-    __shared__ __align__(16) T lds[2][LY][LX];
-
-    const int lb = xcd_remap((int)blockIdx.x, (int)gridDim.x);
-    const ItemDesc &it = items[find_item(items, nitems, lb)];
-    const int nchunks = (it.nsteps + S - 1) / S;
-    if (chunk >= nchunks) return;
-    const int local = lb - it.block_begin;
-    if (local < 0 || local >= it.nblocks) return;
-
-    const int nx = it.nx, ny = it.ny, nz = it.nz;
-    const int txt = local % it.tiles_x;
-    const int rest = local / it.tiles_x;
-    const int tyt = rest % it.tiles_y;
-    const int zc = rest / it.tiles_y;
-    const int x0 = txt * TX, y0 = tyt * TY;
-    const int z0 = zc * it.tz;
-    const int zend = min(z0 + it.tz, nz);
-
-    const T *src;
-    T *dst;
-    pingpong<T>(it, chunk, nchunks, src, dst);
-
-    const int tid = (int)threadIdx.x;
-    const int txi = tid % BXT, tyi = tid / BXT;
-    const int cx0 = txi * NXP, ry0 = tyi * NY;
-    const int gx0 = wrapi(x0 - H + cx0, nx);
-    int rowoff[NY];
-    bool yok[NY];
-#pragma unroll
-    for (int iy = 0; iy < NY; ++iy) {
-        const int ry = ry0 + iy;
-        rowoff[iy] = wrapi(y0 - H + ry, ny) * nx + gx0;
-        yok[iy] = (ry >= H) && (ry < H + TY) && (y0 + ry - H < ny);
-    }
-    const bool xok = (cx0 >= H) && (cx0 < H + TX) && (x0 + cx0 - H < nx);
-    const int nxy = nx * ny;
-
-    Wts<T, 1> w[S];
-    T dts[S];
-#pragma unroll
-    for (int s = 0; s < S; ++s) {
-        const int64_t j = (int64_t)chunk * S + s;
-        const bool act = j < it.nsteps;
-        const double nu = nu_at(it, (double)(it.step0 + j) * it.dt);
-        w[s] = uni(coarse_weights<T>(it, nu));
-        dts[s] = uni(act ? (T)it.dt : (T)0);
-    }
-
-    T f[S][L][NY][NXP];
-    T pf[NY][NXP];
-
-    auto load_plane = [&](int p) {
-        const T *base = src + (size_t)wrapi(p, nz) * nxy;
-#pragma unroll
-        for (int iy = 0; iy < NY; ++iy) {
-            const Vec<T, NXP> v = gld<Vec<T, NXP>>(base + rowoff[iy]);
-#pragma unroll
-            for (int ix = 0; ix < NXP; ++ix) pf[iy][ix] = v.v[ix];
-        }
-    };
-
-    auto body = [&](auto Mc, int p) {
-        constexpr int M = decltype(Mc)::value;
-#pragma unroll
-        for (int iy = 0; iy < NY; ++iy)
-#pragma unroll
-            for (int ix = 0; ix < NXP; ++ix) f[0][slot<L>(M, 0)][iy][ix] = pf[iy][ix];
-        load_plane(p + 1);
-
-        [&]<int... Ss>(std::integer_sequence<int, Ss...>) {
-            (
-                [&] {
-                    constexpr int s = Ss + 1;          // stage s computes plane p - s from f[s-1]
-                    constexpr int sc = slot<L>(M, s);
-                    constexpr int B = s & 1;
-                    const bool active = p >= z0 - S + 2 * s;
-                    if (active) {
-#pragma unroll
-                        for (int iy = 0; iy < NY; ++iy) {
-                            Vec<T, NXP> v;
-#pragma unroll
-                            for (int ix = 0; ix < NXP; ++ix) v.v[ix] = f[s - 1][sc][iy][ix];
-                            *reinterpret_cast<Vec<T, NXP> *>(&lds[B][R + ry0 + iy][CO + cx0]) = v;
-                        }
-                    }
-                    __syncthreads();
-                    if (active) {
-                        T res[NY][NXP];
-#pragma unroll
-                        for (int iy = 0; iy < NY; ++iy) {
-#pragma unroll
-                            for (int ix = 0; ix < NXP; ++ix) {
-                                T mn[3][1], pn[3][1];
-                                mn[0][0] = (ix >= 1) ? f[s - 1][sc][iy][ix - 1] : lds[B][R + ry0 + iy][CO + cx0 + ix - 1];
-                                pn[0][0] = (ix + 1 < NXP) ? f[s - 1][sc][iy][ix + 1] : lds[B][R + ry0 + iy][CO + cx0 + ix + 1];
-                                mn[1][0] = (iy >= 1) ? f[s - 1][sc][iy - 1][ix] : lds[B][R + ry0 + iy - 1][CO + cx0 + ix];
-                                pn[1][0] = (iy + 1 < NY) ? f[s - 1][sc][iy + 1][ix] : lds[B][R + ry0 + iy + 1][CO + cx0 + ix];
-                                mn[2][0] = f[s - 1][slot<L>(M, s + 1)][iy][ix];
-                                pn[2][0] = f[s - 1][slot<L>(M, s - 1)][iy][ix];
-                                const T cen = f[s - 1][sc][iy][ix];
-                                const T Sv = apply<T, 1>(w[s - 1], cen, mn, pn);
-                                res[iy][ix] = fmaT(dts[s - 1], Sv, cen);
-                            }
-                        }
-                        if constexpr (s < S) {
-#pragma unroll
-                            for (int iy = 0; iy < NY; ++iy)
-#pragma unroll
-                                for (int ix = 0; ix < NXP; ++ix) f[s][slot<L>(M, s)][iy][ix] = res[iy][ix];
-                        } else {
-                            const int q = p - S;
-                            if (q < zend && xok) {
-                                T *obase = dst + (size_t)q * nxy;
-#pragma unroll
-                                for (int iy = 0; iy < NY; ++iy) {
-                                    if (yok[iy]) {
-                                        Vec<T, NXP> v;
-#pragma unroll
-                                        for (int ix = 0; ix < NXP; ++ix) v.v[ix] = res[iy][ix];
-                                        gst<Vec<T, NXP>>(obase + rowoff[iy], v);
-                                    }
-                                }
-                            }
-                        }
-                    }
-                }(),
-                ...);
-        }(std::make_integer_sequence<int, S>{});
-    };
-
-    const int pstart = z0 - S;
-    const int niter = (zend - z0) + 2 * S;
-    load_plane(pstart);
-    for (int pb = 0; pb < niter; pb += L) {
-        [&]<int... Ms>(std::integer_sequence<int, Ms...>) {
-            (body(ic<Ms>{}, pstart + pb + Ms), ...);
-        }(std::make_integer_sequence<int, L>{});
-    }
-}
-
-// ---------------------------------------------------------------------------
 // Unfused reference kernels: one thread per point, neighbours read from
 // global memory.  RK4 runs as four stage launches through three scratch
 // fields [Ya | Yb | Acc]; Euler as one launch per step.
@@ -2438,27 +1895,11 @@ void fine_launch_1b(const ItemDesc *items, int nitems, int nblocks, int jstep, h
                        nitems, jstep);
 }
 
-template <typename T, int NXP, int NY, int BXT, int BY, int PD, int PAD>
-void fine_launch_1c(const ItemDesc *items, int nitems, int nblocks, int jstep, hipStream_t s, int *occ)
-{
-    if (occ) return occupancy_of((rk4_step_fused1c<T, NXP, NY, BXT, BY, PD, PAD>), BXT * BY, occ);
-    hipLaunchKernelGGL((rk4_step_fused1c<T, NXP, NY, BXT, BY, PD, PAD>), dim3(nblocks), dim3(BXT * BY), 0, s, items,
-                       nitems, jstep);
-}
-
 template <typename T, int S, int NXP, int NY, int BXT, int BY, int PD>
 void coarse_launch_1b(const ItemDesc *items, int nitems, int nblocks, int chunk, hipStream_t s, int *occ)
 {
     if (occ) return occupancy_of((euler_chunk_fused1b<T, S, NXP, NY, BXT, BY, PD>), BXT * BY, occ);
     hipLaunchKernelGGL((euler_chunk_fused1b<T, S, NXP, NY, BXT, BY, PD>), dim3(nblocks), dim3(BXT * BY), 0, s, items,
-                       nitems, chunk);
-}
-
-template <typename T, int S, int NXP, int NY, int BXT, int BY>
-void coarse_launch(const ItemDesc *items, int nitems, int nblocks, int chunk, hipStream_t s, int *occ)
-{
-    if (occ) return occupancy_of((euler_chunk_fused<T, S, NXP, NY, BXT, BY>), BXT * BY, occ);
-    hipLaunchKernelGGL((euler_chunk_fused<T, S, NXP, NY, BXT, BY>), dim3(nblocks), dim3(BXT * BY), 0, s, items,
                        nitems, chunk);
 }
 
@@ -2477,16 +1918,6 @@ struct CoarseEntry {
 #define FINE_1B(T, DT, NXP, NY, BXT, BY, PD, NAME)                                                       \
     FineEntry{VariantInfo{NAME, DT, 2, BXT * NXP - 8, BY * NY - 8, NXP, BXT * BY, 1},                  \
               &fine_launch_1b<T, NXP, NY, BXT, BY, PD>}
-template <typename T, int S, int NXP, int NY, int BXT, int BY, int PD>
-void coarse_launch_1c(const ItemDesc *items, int nitems, int nblocks, int chunk, hipStream_t s, int *occ)
-{
-    if (occ) return occupancy_of((euler_chunk_fused1c<T, S, NXP, NY, BXT, BY, PD>), BXT * BY, occ);
-    hipLaunchKernelGGL((euler_chunk_fused1c<T, S, NXP, NY, BXT, BY, PD>), dim3(nblocks), dim3(BXT * BY), 0, s, items,
-                       nitems, chunk);
-}
-#define COARSE_1C(T, DT, S, NXP, NY, BXT, BY, PD, NAME)                                                   \
-    CoarseEntry{VariantInfo{NAME, DT, 0, BXT * NXP - 2 * S, BY * NY - 2 * S, NXP, BXT * BY, S},          \
-                &coarse_launch_1c<T, S, NXP, NY, BXT, BY, PD>}
 template <typename T, int NXP, int NY, int NW, int PD>
 void fine_launch_rows(const ItemDesc *items, int nitems, int nblocks, int jstep, hipStream_t s, int *occ)
 {
@@ -2527,9 +1958,6 @@ void fine_launch_half_rows(const ItemDesc *items, int nitems, int nblocks, int j
 #define FINE_HALF_ROWS(T, DT, R, NXP, NW, PD, NAME)                                                      \
     FineEntry{VariantInfo{NAME, DT, 2 * R, 64 * NXP, NW - 4 * R, NXP, 64 * NW, 1, 64 * NXP, 2},        \
               &fine_launch_half_rows<T, R, NXP, NW, PD>}
-#define FINE_1C(T, DT, NXP, NY, BXT, BY, PD, PAD, NAME)                                                  \
-    FineEntry{VariantInfo{NAME, DT, 2, BXT * NXP - 8, BY * NY - 8, NXP, BXT * BY, 1},                  \
-              &fine_launch_1c<T, NXP, NY, BXT, BY, PD, PAD>}
 template <typename T, int S, int NXP, int NY, int NW, int PD>
 void coarse_launch_rows(const ItemDesc *items, int nitems, int nblocks, int chunk, hipStream_t s, int *occ)
 {
@@ -2543,102 +1971,50 @@ void coarse_launch_rows(const ItemDesc *items, int nitems, int nblocks, int chun
 #define COARSE_1B(T, DT, S, NXP, NY, BXT, BY, PD, NAME)                                                   \
     CoarseEntry{VariantInfo{NAME, DT, 0, BXT * NXP - 2 * S, BY * NY - 2 * S, NXP, BXT * BY, S},          \
                 &coarse_launch_1b<T, S, NXP, NY, BXT, BY, PD>}
-#define COARSE_V(T, DT, S, NXP, NY, BXT, BY, NAME)                                                        \
-    CoarseEntry{VariantInfo{NAME, DT, 0, BXT * NXP - 2 * S, BY * NY - 2 * S, NXP, BXT * BY, S},          \
-                &coarse_launch<T, S, NXP, NY, BXT, BY>}
 
 // index 0 and 1 are reserved (automatic, unfused reference)
 const FineEntry kFine[] = {
-    FINE_V(double, 2, 1, 2, 2, 20, 20, "rk4_f64_o2_t32x32_p2x2"),
-    FINE_V(double, 2, 1, 2, 2, 36, 12, "rk4_f64_o2_t64x16_p2x2"),
-    FINE_V(double, 2, 1, 1, 4, 40, 10, "rk4_f64_o2_t32x32_p1x4"),
-    FINE_V(float, 1, 1, 2, 2, 20, 20, "rk4_f32_o2_t32x32_p2x2"),
-    FINE_V(float, 1, 1, 2, 4, 36, 10, "rk4_f32_o2_t64x32_p2x4"),
-    FINE_V(float, 1, 1, 4, 2, 18, 20, "rk4_f32_o2_t64x32_p4x2"),
-    FINE_V(float, 1, 1, 1, 4, 40, 10, "rk4_f32_o2_t32x32_p1x4"),
+    // first fused form (four barriers per plane): fourth order on grids without a whole-row kernel
     FINE_V(double, 2, 2, 2, 1, 24, 32, "rk4_f64_o4_t32x16_p2x1"),
     FINE_V(double, 2, 2, 1, 1, 40, 24, "rk4_f64_o4_t24x8_p1x1"),
-    FINE_V(float, 1, 2, 2, 2, 24, 16, "rk4_f32_o4_t32x16_p2x2"),
     FINE_V(float, 1, 2, 1, 2, 48, 16, "rk4_f32_o4_t32x16_p1x2"),
+    // one barrier per plane, any radius
     FINE_1R(float, 1, 2, 2, 2, 24, 16, 2, "rk4r_f32_o4_t32x16_p2x2_d2"),
-    FINE_1R(double, 2, 1, 1, 2, 40, 20, 2, "rk4r_f64_o2_t32x32_p1x2_d2"),
-    FINE_1B(double, 2, 2, 2, 20, 20, 1, "rk4b_f64_t32x32_p2x2"),
+    // one barrier per plane, radius 1, 2-D tiles
     FINE_1B(double, 2, 2, 2, 20, 20, 2, "rk4b_f64_t32x32_p2x2_d2"),
-    FINE_1B(double, 2, 2, 2, 20, 20, 4, "rk4b_f64_t32x32_p2x2_d4"),
-    FINE_1B(double, 2, 1, 4, 40, 10, 2, "rk4b_f64_t32x32_p1x4_d2"),
-    FINE_1B(double, 2, 2, 2, 36, 12, 2, "rk4b_f64_t64x16_p2x2_d2"),
-    FINE_1B(double, 2, 2, 1, 20, 40, 2, "rk4b_f64_t32x32_p2x1_d2"),
-    FINE_1B(double, 2, 2, 1, 20, 40, 4, "rk4b_f64_t32x32_p2x1_d4"),
     FINE_1B(double, 2, 1, 2, 40, 20, 2, "rk4b_f64_t32x32_p1x2_d2"),
-    FINE_1B(float, 1, 2, 4, 36, 10, 2, "rk4b_f32_t64x32_p2x4_d2"),
-    FINE_1B(float, 1, 4, 2, 18, 20, 2, "rk4b_f32_t64x32_p4x2_d2"),
-    FINE_1B(float, 1, 2, 2, 20, 20, 2, "rk4b_f32_t32x32_p2x2_d2"),
     FINE_1B(float, 1, 1, 4, 40, 10, 2, "rk4b_f32_t32x32_p1x4_d2"),
-    FINE_1B(float, 1, 2, 2, 36, 20, 1, "rk4b_f32_t64x32_p2x2"),
     FINE_1B(float, 1, 2, 2, 36, 20, 2, "rk4b_f32_t64x32_p2x2_d2"),
-    FINE_1B(float, 1, 2, 2, 36, 20, 4, "rk4b_f32_t64x32_p2x2_d4"),
-    FINE_1B(float, 1, 4, 1, 18, 40, 2, "rk4b_f32_t64x32_p4x1_d2"),
     FINE_1B(float, 1, 2, 2, 28, 16, 2, "rk4b_f32_t48x24_p2x2_d2"),
     FINE_1B(float, 1, 2, 2, 28, 20, 2, "rk4b_f32_t48x32_p2x2_d2"),
     FINE_1B(float, 1, 2, 2, 36, 16, 2, "rk4b_f32_t64x24_p2x2_d2"),
-    FINE_1C(double, 2, 1, 2, 40, 20, 2, 2, "rk4c_f64_t32x32_p1x2_pad2"),
-    FINE_1C(double, 2, 1, 2, 40, 20, 2, 6, "rk4c_f64_t32x32_p1x2_pad6"),
-    FINE_1C(double, 2, 2, 2, 20, 20, 2, 2, "rk4c_f64_t32x32_p2x2_pad2"),
-    FINE_1C(double, 2, 2, 1, 20, 40, 2, 2, "rk4c_f64_t32x32_p2x1_pad2"),
-    FINE_1C(double, 2, 2, 2, 36, 12, 2, 2, "rk4c_f64_t64x16_p2x2_pad2"),
-    FINE_1C(float, 1, 2, 2, 36, 20, 2, 4, "rk4c_f32_t64x32_p2x2_pad4"),
-    FINE_1C(float, 1, 2, 2, 36, 20, 2, 8, "rk4c_f32_t64x32_p2x2_pad8"),
-    FINE_1C(float, 1, 2, 2, 36, 20, 2, 2, "rk4c_f32_t64x32_p2x2_pad2"),
-    FINE_1C(float, 1, 2, 2, 36, 20, 2, 0, "rk4c_f32_t64x32_p2x2_pad0"),
-    FINE_1C(float, 1, 4, 2, 18, 20, 2, 4, "rk4c_f32_t64x32_p4x2_pad4"),
-    FINE_1C(float, 1, 2, 4, 36, 10, 2, 4, "rk4c_f32_t64x32_p2x4_pad4"),
+    // whole rows, radius 1
     FINE_ROWS(double, 2, 2, 1, 16, 2, "rk4w_f64_x128_y8_p2x1_w16"),
-    FINE_ROWS(double, 2, 2, 1, 16, 1, "rk4w_f64_x128_y8_p2x1_w16_d1"),
-    FINE_ROWS(double, 2, 2, 2, 8, 2, "rk4w_f64_x128_y8_p2x2_w8"),
-    FINE_ROWS(double, 2, 1, 1, 16, 2, "rk4w_f64_x64_y8_p1x1_w16"),
     FINE_ROWS(double, 2, 1, 2, 8, 2, "rk4w_f64_x64_y8_p1x2_w8"),
-    FINE_ROWS(double, 2, 1, 3, 8, 2, "rk4w_f64_x64_y16_p1x3_w8"),
+    FINE_ROWS(double, 2, 1, 2, 12, 2, "rk4w_f64_x64_y16_p1x2_w12"),
     FINE_ROWS(float, 1, 4, 2, 8, 2, "rk4w_f32_x256_y8_p4x2_w8"),
-    FINE_ROWS(float, 1, 2, 1, 16, 2, "rk4w_f32_x128_y8_p2x1_w16"),
     FINE_ROWS(float, 1, 2, 2, 8, 2, "rk4w_f32_x128_y8_p2x2_w8"),
-    FINE_ROWS(float, 1, 2, 3, 8, 2, "rk4w_f32_x128_y16_p2x3_w8"),
     FINE_ROWS(float, 1, 2, 2, 12, 2, "rk4w_f32_x128_y16_p2x2_w12"),
     FINE_ROWS(float, 1, 1, 2, 12, 2, "rk4w_f32_x64_y16_p1x2_w12"),
     FINE_ROWS(float, 1, 1, 2, 16, 2, "rk4w_f32_x64_y24_p1x2_w16"),
-    FINE_ROWS(double, 2, 1, 2, 12, 2, "rk4w_f64_x64_y16_p1x2_w12"),
-    FINE_HALF_ROWS(double, 2, 2, 2, 16, 2, "rk4h_f64_o4_x128_y8_p2_w16"),
+    // whole rows, radius 2, two launches of two stages
     FINE_HALF_ROWS(double, 2, 2, 2, 16, 1, "rk4h_f64_o4_x128_y8_p2_w16_d1"),
     FINE_HALF_ROWS(float, 1, 2, 2, 16, 2, "rk4h_f32_o4_x128_y8_p2_w16"),
 };
 
 const CoarseEntry kCoarse[] = {
-    COARSE_V(double, 2, 4, 2, 2, 20, 20, "euler4_f64_t32x32_p2x2"),
-    COARSE_V(double, 2, 2, 2, 2, 18, 18, "euler2_f64_t32x32_p2x2"),
-    COARSE_V(double, 2, 1, 1, 2, 34, 17, "euler1_f64_t32x32_p1x2"),
-    COARSE_V(float, 1, 4, 2, 2, 20, 20, "euler4_f32_t32x32_p2x2"),
-    COARSE_V(float, 1, 8, 2, 2, 24, 16, "euler8_f32_t32x16_p2x2"),
-    COARSE_V(float, 1, 2, 2, 2, 18, 18, "euler2_f32_t32x32_p2x2"),
-    COARSE_V(float, 1, 1, 1, 2, 34, 17, "euler1_f32_t32x32_p1x2"),
-    COARSE_V(double, 2, 4, 1, 4, 40, 10, "euler4_f64_t32x32_p1x4"),
-    COARSE_V(float, 1, 4, 1, 4, 40, 10, "euler4_f32_t32x32_p1x4"),
+    // one barrier per plane, 2-D tiles (S Euler steps per launch)
     COARSE_1B(double, 2, 4, 2, 2, 20, 20, 2, "euler4b_f64_t32x32_p2x2_d2"),
+    COARSE_1B(double, 2, 4, 1, 4, 40, 10, 2, "euler4b_f64_t32x32_p1x4_d2"),
     COARSE_1B(double, 2, 2, 2, 2, 18, 18, 2, "euler2b_f64_t32x32_p2x2_d2"),
     COARSE_1B(float, 1, 4, 2, 2, 20, 20, 2, "euler4b_f32_t32x32_p2x2_d2"),
-    COARSE_1B(float, 1, 8, 2, 2, 24, 16, 2, "euler8b_f32_t32x16_p2x2_d2"),
-    COARSE_1B(double, 2, 4, 2, 2, 20, 20, 3, "euler4b_f64_t32x32_p2x2_d3"),
-    COARSE_1B(double, 2, 4, 1, 4, 40, 10, 2, "euler4b_f64_t32x32_p1x4_d2"),
     COARSE_1B(float, 1, 4, 1, 4, 40, 10, 2, "euler4b_f32_t32x32_p1x4_d2"),
-    COARSE_1C(double, 2, 4, 2, 2, 20, 20, 2, "euler4c_f64_t32x32_p2x2"),
-    COARSE_1C(double, 2, 4, 1, 2, 40, 20, 2, "euler4c_f64_t32x32_p1x2"),
-    COARSE_1C(double, 2, 2, 2, 2, 18, 18, 2, "euler2c_f64_t32x32_p2x2"),
-    COARSE_1C(float, 1, 4, 2, 2, 20, 20, 2, "euler4c_f32_t32x32_p2x2"),
-    COARSE_1C(float, 1, 2, 2, 2, 18, 18, 2, "euler2c_f32_t32x32_p2x2"),
+    COARSE_1B(float, 1, 8, 2, 2, 24, 16, 2, "euler8b_f32_t32x16_p2x2_d2"),
+    // whole rows
     COARSE_ROWS(double, 2, 4, 2, 1, 16, 2, "euler4w_f64_x128_y8_p2x1_w16"),
     COARSE_ROWS(double, 2, 2, 2, 1, 16, 2, "euler2w_f64_x128_y12_p2x1_w16"),
-    COARSE_ROWS(double, 2, 4, 2, 2, 8, 2, "euler4w_f64_x128_y8_p2x2_w8"),
     COARSE_ROWS(double, 2, 4, 1, 1, 16, 2, "euler4w_f64_x64_y8_p1x1_w16"),
     COARSE_ROWS(float, 1, 4, 4, 1, 16, 2, "euler4w_f32_x256_y8_p4x1_w16"),
-    COARSE_ROWS(float, 1, 4, 4, 2, 8, 2, "euler4w_f32_x256_y8_p4x2_w8"),
     COARSE_ROWS(float, 1, 4, 2, 1, 16, 2, "euler4w_f32_x128_y8_p2x1_w16"),
 };
 

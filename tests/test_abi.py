@@ -380,3 +380,51 @@ def test_static_defect_norm_validation_without_device():
     assert lib.pr_defect_norm_static(0, 1, 2, 1, 2, 1, 1, None) == L.PR_EINVAL
     assert lib.pr_defect_norm_static(10, 1, 3, 1, 2, 1, 1, None) == L.PR_EINVAL
     assert lib.pr_defect_norm_static(10, 1, 2, None, 2, 1, 1, None) == L.PR_EINVAL
+
+
+def test_autotune_cache_round_trip(tmp_path):
+    """The tuned-kernel table is saved as JSON and loaded back; lookups use
+    entries of the current architecture ("none" without a device); entries
+    naming an unknown variant are skipped; PR_AUTOTUNE_CACHE loads a file
+    before the first lookup in a fresh process.  Host logic only."""
+    import json
+    import subprocess
+    import sys
+    import paper_1409_8563_amd as pr
+    p = W.small_problem(n=(40, 36, 20), P=2, nf=4)
+    p.flags |= W.ALLOW_UNSTABLE
+    default = pr.sweep_kernel_variant(p, 1, 4, 0)
+    tuned = "rk4b_f32_t32x32_p1x4_d2"
+    assert default != tuned
+    src = tmp_path / "tune.json"
+    src.write_text(json.dumps({"format": "pr-autotune-1", "entries": [
+        {"arch": "none", "which": 0, "n": [40, 36, 20], "dtype": 1, "order": 2, "batch": 4,
+         "variant": tuned, "blocks_per_cu": 2},
+        {"arch": "gfx942", "which": 0, "n": [40, 36, 20], "dtype": 1, "order": 2, "batch": 4,
+         "variant": "rk4b_f32_t64x32_p2x2_d2", "blocks_per_cu": 0},
+        {"arch": "none", "which": 0, "n": [64, 64, 64], "dtype": 1, "order": 2, "batch": 4,
+         "variant": "no_such_kernel", "blocks_per_cu": 0}]}))
+    try:
+        pr.autotune_clear()
+        assert pr.autotune_load(str(src)) == 2
+        assert pr.sweep_kernel_variant(p, 1, 4, 0) == tuned
+        assert pr.sweep_kernel_variant(p, 1, 7, 0) == tuned        # any tuned batch of the shape
+        out = tmp_path / "saved.json"
+        pr.autotune_save(str(out))
+        saved = json.loads(out.read_text())
+        key = lambda e: json.dumps(e, sort_keys=True)
+        assert sorted(map(key, saved["entries"])) == sorted(map(key, json.loads(src.read_text())["entries"][:2]))
+        pr.autotune_clear()
+        assert pr.sweep_kernel_variant(p, 1, 4, 0) == default
+        assert pr.autotune_load(str(out)) == 2
+        assert pr.sweep_kernel_variant(p, 1, 4, 0) == tuned
+    finally:
+        pr.autotune_clear()
+    with pytest.raises(Exception):
+        pr.autotune_load(str(tmp_path / "missing.json"))
+    code = ("import sys; sys.path.insert(0, %r); import workloads as W, paper_1409_8563_amd as pr\n"
+            "p = W.small_problem(n=(40, 36, 20), P=2, nf=4); p.flags |= W.ALLOW_UNSTABLE\n"
+            "print(pr.sweep_kernel_variant(p, 1, 4, 0))" % ROOT)
+    env = dict(os.environ, PR_AUTOTUNE_CACHE=str(out))
+    got = subprocess.run([sys.executable, "-c", code], env=env, capture_output=True, text=True, timeout=120)
+    assert got.stdout.strip().splitlines()[-1] == tuned, got.stderr
