@@ -449,7 +449,8 @@ bool coarse_applicable(int v, int dtype, const pr_problem &p)
     return vi && vi->dtype == dtype && p.n[0] % vi->nxp == 0 && (vi->rowx == 0 || p.n[0] == vi->rowx);
 }
 
-// Built-in choice (measured on the five workloads); batch = fields per launch.
+// Built-in choice (measured on the five workloads and on batches of the
+// uneven workload's grid sizes); batch = fields per launch.
 int pick_fine_default(const pr_problem &p, int dtype, int batch)
 {
     const int order = p.fine_order;
@@ -461,9 +462,15 @@ int pick_fine_default(const pr_problem &p, int dtype, int batch)
                                              : "rk4_f64_o4_t24x8_p1x1")
                : p.n[0] == 128 ? "rk4w_f64_x128_y8_p2x1_w16"
                : p.n[0] == 64  ? (batch >= 4 ? "rk4w_f64_x64_y16_p1x2_w12" : "rk4w_f64_x64_y8_p1x2_w8")
+               : p.n[0] == 48  ? "rk4s_f64_x48_y24_p3x1_w8"
+               : p.n[0] == 32  ? "rk4s_f64_x32_y32_p2x1_w10"
                                : "rk4b_f64_t32x32_p1x2_d2";
     else if (order == 2 && p.n[0] == 64)
-        name = batch >= 64 ? "rk4w_f32_x64_y24_p1x2_w16" : "rk4w_f32_x64_y16_p1x2_w12";
+        name = batch >= 64 ? "rk4s_f32_x64_y24_p4x1_w8" : "rk4s_f32_x64_y40_p4x1_w12";
+    else if (order == 2 && (p.n[0] == 96 || p.n[0] == 48 || p.n[0] == 32))
+        name = p.n[0] == 96 ? "rk4s_f32_x96_y24_p6x1_w8"
+               : p.n[0] == 48 ? "rk4s_f32_x48_y24_p3x1_w8"
+                              : "rk4s_f32_x32_y32_p2x1_w10";
     else if (order == 2 && even && p.n[0] != 256 && p.n[0] != 128) {
         // two x points per thread, tiled: the tile that computes the fewest
         // points per output point of this grid in x and y (halo of 4 per side)

@@ -693,6 +693,71 @@ __global__ void __launch_bounds__(BXT *BY)
 // ---------------------------------------------------------------------------
 constexpr int kDppWaveRor1 = 0x13C;  // lane l receives the value of lane (l - 1) mod 64
 constexpr int kDppWaveRol1 = 0x134;  // lane l receives the value of lane (l + 1) mod 64
+// rotations inside each row of 16 lanes (lane l, row base b = l & ~15):
+constexpr int kDppRowRor1 = 0x121;   // lane l receives lane b + (l - 1) mod 16
+constexpr int kDppRowRor15 = 0x12F;  // lane l receives lane b + (l + 1) mod 16
+
+// N consecutive elements of a row moved in the widest aligned pieces: four
+// or two elements when N is a multiple of that (the start is then aligned to
+// the piece, since it is a multiple of N elements into a 16-byte aligned
+// row), single elements otherwise.
+template <int N>
+constexpr int piece_of() { return N % 4 == 0 ? 4 : (N % 2 == 0 ? 2 : 1); }
+
+template <typename T, int N>
+__device__ __forceinline__ void gld_row(const T *p, T (&d)[N])
+{
+    constexpr int C = piece_of<N>();
+#pragma unroll
+    for (int k = 0; k < N / C; ++k) {
+        if constexpr (C == 1) {
+            d[k] = *(const PR_GLOBAL T *)(p + k);
+        } else {
+            const ExtVec<T, C> e = *(const PR_GLOBAL ExtVec<T, C> *)(p + k * C);
+#pragma unroll
+            for (int i = 0; i < C; ++i) d[k * C + i] = e[i];
+        }
+    }
+}
+template <typename T, int N>
+__device__ __forceinline__ void gst_nt_row(T *p, const T (&v)[N])
+{
+    constexpr int C = piece_of<N>();
+#pragma unroll
+    for (int k = 0; k < N / C; ++k) {
+        if constexpr (C == 1) {
+            __builtin_nontemporal_store(v[k], (PR_GLOBAL T *)(p + k));
+        } else {
+            ExtVec<T, C> e;
+#pragma unroll
+            for (int i = 0; i < C; ++i) e[i] = v[k * C + i];
+            __builtin_nontemporal_store(e, (PR_GLOBAL ExtVec<T, C> *)(p + k * C));
+        }
+    }
+}
+template <typename T, int N>
+__device__ __forceinline__ void lds_st_row(T *p, const T (&v)[N])
+{
+    constexpr int C = piece_of<N>();
+#pragma unroll
+    for (int k = 0; k < N / C; ++k) {
+        Vec<T, C> e;
+#pragma unroll
+        for (int i = 0; i < C; ++i) e.v[i] = v[k * C + i];
+        *reinterpret_cast<Vec<T, C> *>(p + k * C) = e;
+    }
+}
+template <typename T, int N>
+__device__ __forceinline__ void lds_ld_row(const T *p, T (&d)[N])
+{
+    constexpr int C = piece_of<N>();
+#pragma unroll
+    for (int k = 0; k < N / C; ++k) {
+        const Vec<T, C> e = *reinterpret_cast<const Vec<T, C> *>(p + k * C);
+#pragma unroll
+        for (int i = 0; i < C; ++i) d[k * C + i] = e.v[i];
+    }
+}
 
 template <int CTRL>
 __device__ __forceinline__ float wave_rot(float v)
@@ -709,19 +774,22 @@ __device__ __forceinline__ double wave_rot(double v)
     return __builtin_bit_cast(double, ((long long)hi << 32) | (unsigned int)lo);
 }
 
-template <typename T, int NXP, int NY, int NW, int PD>
+template <typename T, int NXP, int NY, int NW, int PD, int SEG>
 __global__ void __launch_bounds__(64 * NW)
     rk4_step_rows(const ItemDesc *__restrict__ items, int nitems, int jstep)
 {
     static_assert(4 % PD == 0, "prefetch depth must divide the unroll");
+    static_assert(SEG == 64 || SEG == 16, "a grid row spans a wavefront or a 16-lane DPP row");
     constexpr int R = 1;
     constexpr int H = 4;
-    constexpr int NX = 64 * NXP;
-    constexpr int EY = NW * NY, TY = EY - 2 * H;
+    constexpr int RG = 64 / SEG;          // grid rows side by side in a wavefront
+    constexpr int NVW = NW * RG;          // row groups of the block
+    constexpr int NX = SEG * NXP;
+    constexpr int EY = NVW * NY, TY = EY - 2 * H;
     constexpr int L = 4;                  // z-ring length (even: LDS slot = phase parity)
-    constexpr int NE = NY == 1 ? 1 : 2;   // exchanged rows per wavefront: first, last
+    constexpr int NE = NY == 1 ? 1 : 2;   // exchanged rows per row group: first, last
     static_assert(TY > 0, "tile too small for the halo");
-    __shared__ __align__(16) T lds[4][2][NW][NE][NX];   // [stage input][slot][wavefront][edge][x]
+    __shared__ __align__(16) T lds[4][2][NVW][NE][NX];   // [stage input][slot][row group][edge][x]
 
     const int lb = xcd_remap((int)blockIdx.x, (int)gridDim.x);
     const ItemDesc &it = items[find_item(items, nitems, lb)];
@@ -742,10 +810,11 @@ __global__ void __launch_bounds__(64 * NW)
 
     const int lane = (int)threadIdx.x & 63;
     const int wv = __builtin_amdgcn_readfirstlane((int)threadIdx.x >> 6);
-    const int wup = wv > 0 ? wv - 1 : 0;          // clamped: wavefront 0 never uses its upper neighbour
-    const int wdn = wv < NW - 1 ? wv + 1 : NW - 1;
-    const int ry0 = wv * NY;
-    const int cx0 = lane * NXP;
+    const int vw = wv * RG + lane / SEG;          // row group (the wavefront itself for SEG = 64)
+    const int wup = vw > 0 ? vw - 1 : 0;          // clamped: row group 0 never uses its upper neighbour
+    const int wdn = vw < NVW - 1 ? vw + 1 : NVW - 1;
+    const int ry0 = vw * NY;
+    const int cx0 = (lane % SEG) * NXP;
     int rowoff[NY];
     bool rowout[NY];
 #pragma unroll
@@ -755,8 +824,10 @@ __global__ void __launch_bounds__(64 * NW)
         rowout[iy] = (ry >= H) && (ry < H + TY) && (y0 + ry - H < ny);
     }
     const int nxy = NX * ny;
-    // stage s (1..4) can feed an output point only on rows s .. EY-1-s
-    auto wave_active = [&](int s) { return ry0 + NY - 1 >= s && ry0 < EY - s; };
+    // stage s (1..4) can feed an output point only on rows s .. EY-1-s; a
+    // wavefront runs a stage if any of its rows needs it
+    const int wr0 = wv * RG * NY;
+    auto wave_active = [&](int s) { return wr0 + RG * NY - 1 >= s && wr0 < EY - s; };
     const bool act1 = wave_active(1), act2 = wave_active(2), act3 = wave_active(3), act4 = wave_active(4);
 
     const double dt = it.dt;
@@ -782,39 +853,27 @@ __global__ void __launch_bounds__(64 * NW)
     auto load_plane = [&](int p, T(&dstp)[NY][NXP]) {
         const T *base = src + (size_t)wrapi(p, nz) * nxy;
 #pragma unroll
-        for (int iy = 0; iy < NY; ++iy) {
-            const Vec<T, NXP> v = gld<Vec<T, NXP>>(base + rowoff[iy]);
-#pragma unroll
-            for (int ix = 0; ix < NXP; ++ix) dstp[iy][ix] = v.v[ix];
-        }
+        for (int iy = 0; iy < NY; ++iy) gld_row<T, NXP>(base + rowoff[iy], dstp[iy]);
     };
 
-    // first and last row of this wavefront's values of a plane -> LDS
+    // first and last row of this row group's values of a plane -> LDS
     auto put = [&](auto Bc, auto SLc, const T(&v)[NY][NXP]) {
         constexpr int B = decltype(Bc)::value;
         constexpr int SL = decltype(SLc)::value;
-        Vec<T, NXP> a;
-#pragma unroll
-        for (int ix = 0; ix < NXP; ++ix) a.v[ix] = v[0][ix];
-        *reinterpret_cast<Vec<T, NXP> *>(&lds[B][SL][wv][0][cx0]) = a;
-        if constexpr (NE == 2) {
-            Vec<T, NXP> b;
-#pragma unroll
-            for (int ix = 0; ix < NXP; ++ix) b.v[ix] = v[NY - 1][ix];
-            *reinterpret_cast<Vec<T, NXP> *>(&lds[B][SL][wv][1][cx0]) = b;
-        }
+        lds_st_row<T, NXP>(&lds[B][SL][vw][0][cx0], v[0]);
+        if constexpr (NE == 2) lds_st_row<T, NXP>(&lds[B][SL][vw][1][cx0], v[NY - 1]);
     };
 
-    // rows above and below this wavefront of a plane of stage input B, slot SL
+    // rows above and below this row group of a plane of stage input B, slot SL
     struct Nb {
-        Vec<T, NXP> up, dn;
+        T up[NXP], dn[NXP];
     };
     auto fetch = [&](auto Bc, auto SLc) {
         constexpr int B = decltype(Bc)::value;
         constexpr int SL = decltype(SLc)::value;
         Nb nb;
-        nb.up = *reinterpret_cast<const Vec<T, NXP> *>(&lds[B][SL][wup][NE - 1][cx0]);
-        nb.dn = *reinterpret_cast<const Vec<T, NXP> *>(&lds[B][SL][wdn][0][cx0]);
+        lds_ld_row<T, NXP>(&lds[B][SL][wup][NE - 1][cx0], nb.up);
+        lds_ld_row<T, NXP>(&lds[B][SL][wdn][0][cx0], nb.dn);
         return nb;
     };
 
@@ -828,15 +887,15 @@ __global__ void __launch_bounds__(64 * NW)
         constexpr int SCP = decltype(SCPc)::value;
 #pragma unroll
         for (int iy = 0; iy < NY; ++iy) {
-            const T left = wave_rot<kDppWaveRor1>(in[SC][iy][NXP - 1]);
-            const T right = wave_rot<kDppWaveRol1>(in[SC][iy][0]);
+            const T left = wave_rot<SEG == 64 ? kDppWaveRor1 : kDppRowRor1>(in[SC][iy][NXP - 1]);
+            const T right = wave_rot<SEG == 64 ? kDppWaveRol1 : kDppRowRor15>(in[SC][iy][0]);
 #pragma unroll
             for (int ix = 0; ix < NXP; ++ix) {
                 T mn[3][1], pn[3][1];
                 mn[0][0] = (ix >= 1) ? in[SC][iy][ix - 1] : left;
                 pn[0][0] = (ix + 1 < NXP) ? in[SC][iy][ix + 1] : right;
-                mn[1][0] = (iy >= 1) ? in[SC][iy - 1][ix] : nb.up.v[ix];
-                pn[1][0] = (iy + 1 < NY) ? in[SC][iy + 1][ix] : nb.dn.v[ix];
+                mn[1][0] = (iy >= 1) ? in[SC][iy - 1][ix] : nb.up[ix];
+                pn[1][0] = (iy + 1 < NY) ? in[SC][iy + 1][ix] : nb.dn[ix];
                 mn[2][0] = in[SCM][iy][ix];
                 pn[2][0] = in[SCP][iy][ix];
                 S[iy][ix] = apply<T, 1>(w, in[SC][iy][ix], mn, pn);
@@ -906,11 +965,10 @@ __global__ void __launch_bounds__(64 * NW)
 #pragma unroll
             for (int iy = 0; iy < NY; ++iy) {
                 if (rowout[iy]) {
-                    Vec<T, NXP> v;
+                    T v[NXP];
 #pragma unroll
-                    for (int ix = 0; ix < NXP; ++ix)
-                        v.v[ix] = fmaT(kc.b4, S[iy][ix], ac[slot<L>(M, 4)][iy][ix]);
-                    gst_nt<Vec<T, NXP>>(obase + rowoff[iy], v);
+                    for (int ix = 0; ix < NXP; ++ix) v[ix] = fmaT(kc.b4, S[iy][ix], ac[slot<L>(M, 4)][iy][ix]);
+                    gst_nt_row<T, NXP>(obase + rowoff[iy], v);
                 }
             }
         };
@@ -1918,16 +1976,20 @@ struct CoarseEntry {
 #define FINE_1B(T, DT, NXP, NY, BXT, BY, PD, NAME)                                                       \
     FineEntry{VariantInfo{NAME, DT, 2, BXT * NXP - 8, BY * NY - 8, NXP, BXT * BY, 1},                  \
               &fine_launch_1b<T, NXP, NY, BXT, BY, PD>}
-template <typename T, int NXP, int NY, int NW, int PD>
+template <typename T, int NXP, int NY, int NW, int PD, int SEG>
 void fine_launch_rows(const ItemDesc *items, int nitems, int nblocks, int jstep, hipStream_t s, int *occ)
 {
-    if (occ) return occupancy_of((rk4_step_rows<T, NXP, NY, NW, PD>), 64 * NW, occ);
-    hipLaunchKernelGGL((rk4_step_rows<T, NXP, NY, NW, PD>), dim3(nblocks), dim3(64 * NW), 0, s, items, nitems,
+    if (occ) return occupancy_of((rk4_step_rows<T, NXP, NY, NW, PD, SEG>), 64 * NW, occ);
+    hipLaunchKernelGGL((rk4_step_rows<T, NXP, NY, NW, PD, SEG>), dim3(nblocks), dim3(64 * NW), 0, s, items, nitems,
                        jstep);
 }
 #define FINE_ROWS(T, DT, NXP, NY, NW, PD, NAME)                                                          \
     FineEntry{VariantInfo{NAME, DT, 2, 64 * NXP, NW * NY - 8, NXP, 64 * NW, 1, 64 * NXP},              \
-              &fine_launch_rows<T, NXP, NY, NW, PD>}
+              &fine_launch_rows<T, NXP, NY, NW, PD, 64>}
+// grid rows of 16 lanes, four side by side in a wavefront
+#define FINE_ROWS16(T, DT, NXP, NY, NW, PD, NAME)                                                        \
+    FineEntry{VariantInfo{NAME, DT, 2, 16 * NXP, 4 * NW * NY - 8, NXP, 64 * NW, 1, 16 * NXP},          \
+              &fine_launch_rows<T, NXP, NY, NW, PD, 16>}
 template <typename T, int R, int NXP, int NY, int BXT, int BY, int PD>
 void fine_launch_1r(const ItemDesc *items, int nitems, int nblocks, int jstep, hipStream_t s, int *occ)
 {
@@ -1988,15 +2050,20 @@ const FineEntry kFine[] = {
     FINE_1B(float, 1, 2, 2, 28, 16, 2, "rk4b_f32_t48x24_p2x2_d2"),
     FINE_1B(float, 1, 2, 2, 28, 20, 2, "rk4b_f32_t48x32_p2x2_d2"),
     FINE_1B(float, 1, 2, 2, 36, 16, 2, "rk4b_f32_t64x24_p2x2_d2"),
-    // whole rows, radius 1
+    // whole rows, radius 1 (a grid row spans a wavefront, or a 16-lane DPP row: rk4s_)
     FINE_ROWS(double, 2, 2, 1, 16, 2, "rk4w_f64_x128_y8_p2x1_w16"),
     FINE_ROWS(double, 2, 1, 2, 8, 2, "rk4w_f64_x64_y8_p1x2_w8"),
     FINE_ROWS(double, 2, 1, 2, 12, 2, "rk4w_f64_x64_y16_p1x2_w12"),
     FINE_ROWS(float, 1, 4, 2, 8, 2, "rk4w_f32_x256_y8_p4x2_w8"),
     FINE_ROWS(float, 1, 2, 2, 8, 2, "rk4w_f32_x128_y8_p2x2_w8"),
     FINE_ROWS(float, 1, 2, 2, 12, 2, "rk4w_f32_x128_y16_p2x2_w12"),
-    FINE_ROWS(float, 1, 1, 2, 12, 2, "rk4w_f32_x64_y16_p1x2_w12"),
-    FINE_ROWS(float, 1, 1, 2, 16, 2, "rk4w_f32_x64_y24_p1x2_w16"),
+    FINE_ROWS16(float, 1, 6, 1, 8, 2, "rk4s_f32_x96_y24_p6x1_w8"),
+    FINE_ROWS16(float, 1, 3, 1, 8, 2, "rk4s_f32_x48_y24_p3x1_w8"),
+    FINE_ROWS16(double, 2, 3, 1, 8, 2, "rk4s_f64_x48_y24_p3x1_w8"),
+    FINE_ROWS16(double, 2, 2, 1, 10, 2, "rk4s_f64_x32_y32_p2x1_w10"),
+    FINE_ROWS16(float, 1, 4, 1, 8, 2, "rk4s_f32_x64_y24_p4x1_w8"),
+    FINE_ROWS16(float, 1, 4, 1, 12, 2, "rk4s_f32_x64_y40_p4x1_w12"),
+    FINE_ROWS16(float, 1, 2, 1, 10, 2, "rk4s_f32_x32_y32_p2x1_w10"),
     // whole rows, radius 2, two launches of two stages
     FINE_HALF_ROWS(double, 2, 2, 2, 16, 1, "rk4h_f64_o4_x128_y8_p2_w16_d1"),
     FINE_HALF_ROWS(float, 1, 2, 2, 16, 2, "rk4h_f32_o4_x128_y8_p2_w16"),

@@ -186,8 +186,9 @@ def test_variant_registry():
         assert v["dtype"] in (1, 2) and v["order"] in (2, 4) and v["steps"] == 1
         assert v["tile"][0] > 0 and v["tile"][1] > 0
         if v["nx_exact"]:
-            # whole-row kernels: one lane per nxp consecutive x of a 64-lane wavefront
-            assert v["nx_exact"] == 64 * v["nxp"] == v["tile"][0]
+            # whole-row kernels: a grid row spans a 64-lane wavefront or a
+            # 16-lane DPP row, each lane holding nxp consecutive x
+            assert v["nx_exact"] == v["tile"][0] and v["nx_exact"] in (16 * v["nxp"], 64 * v["nxp"])
     assert any(v["nx_exact"] for v in fine)
     for v in coarse:
         assert v["order"] == 0 and v["steps"] >= 1
@@ -204,17 +205,22 @@ def test_variant_registry():
     ((256, 256, 256), 1, 32, "rk4w_f32_x256_y8_p4x2_w8"),
     ((128, 128, 128), 1, 136, "rk4w_f32_x128_y16_p2x2_w12"),
     ((128, 128, 128), 1, 1, "rk4w_f32_x128_y8_p2x2_w8"),
-    ((96, 96, 96), 1, 88, "rk4b_f32_t48x32_p2x2_d2"),
-    ((64, 64, 64), 1, 152, "rk4w_f32_x64_y24_p1x2_w16"),
-    ((64, 64, 64), 1, 16, "rk4w_f32_x64_y16_p1x2_w12"),
-    ((48, 48, 48), 1, 136, "rk4b_f32_t48x24_p2x2_d2"),
+    ((96, 96, 96), 1, 88, "rk4s_f32_x96_y24_p6x1_w8"),
+    ((64, 64, 64), 1, 152, "rk4s_f32_x64_y24_p4x1_w8"),
+    ((64, 64, 64), 1, 16, "rk4s_f32_x64_y40_p4x1_w12"),
+    ((48, 48, 48), 1, 136, "rk4s_f32_x48_y24_p3x1_w8"),
+    ((48, 48, 48), 2, 8, "rk4s_f64_x48_y24_p3x1_w8"),
+    ((32, 32, 32), 2, 4, "rk4s_f64_x32_y32_p2x1_w10"),
+    ((32, 32, 32), 1, 16, "rk4s_f32_x32_y32_p2x1_w10"),
+    ((80, 60, 40), 1, 16, "rk4b_f32_t48x32_p2x2_d2"),
     ((512, 512, 512), 1, 32, "rk4b_f32_t64x32_p2x2_d2"),
     ((37, 29, 23), 1, 2, "rk4b_f32_t32x32_p1x4_d2"),
 ])
 def test_builtin_fine_kernel_choice(n3, dtype, batch, name):
-    """Host logic, no device: the built-in F kernel for a grid (whole-row for
-    n_x = 64/128/256 as measured; for other FP32 grids the 2-D tile that
-    computes the fewest points per output point)."""
+    """Host logic, no device: the built-in F kernel for a grid (whole rows for
+    n_x = 64/128/256, 16-lane rows for n_x = 32/48/96, as measured; for other
+    FP32 grids the 2-D tile that computes the fewest points per output
+    point)."""
     import paper_1409_8563_amd as pr
     p = W.small_problem(n=n3, P=2, nf=4)
     p.flags |= W.ALLOW_UNSTABLE
@@ -237,7 +243,7 @@ def test_fp32_tile_choice_minimises_computed_points():
 
     for nx in range(8, 200, 6):
         for ny in (10, 24, 48, 72, 100):
-            if nx in (64, 128, 256):
+            if nx in (32, 48, 64, 96, 128, 256):
                 continue
             p = W.small_problem(n=(nx, ny, 12), P=2, nf=4)
             p.flags |= W.ALLOW_UNSTABLE

@@ -135,6 +135,7 @@ def test_fine_variants_bitwise_identical(pr, dtype, order):
 
 @pytest.mark.parametrize("dtype", [1, 2])
 @pytest.mark.parametrize("n3,order", [((128, 52, 21), 2), ((64, 37, 19), 2), ((256, 20, 9), 2), ((128, 8, 5), 2),
+                                      ((96, 52, 21), 2), ((48, 37, 19), 2), ((48, 8, 5), 2), ((96, 100, 6), 2),
                                       ((128, 52, 21), 4), ((128, 8, 5), 4), ((128, 19, 40), 4)])
 def test_fine_whole_row_variants_bitwise_identical(pr, dtype, n3, order):
     """The whole-row kernels (x neighbours across the wavefront; for order 4
@@ -455,8 +456,9 @@ def test_multi_instance_whole_row_kernels(pr, orc):
 
 
 def test_multi_instance_launch_groups(pr, orc):
-    """Instances whose grids call for different F kernels (whole-row at
-    n_x = 128, tiled at n_x = 48) run as separate launch groups of one plan:
+    """Instances whose grids call for different F kernels (whole rows of a
+    wavefront at n_x = 128, of 16 lanes at n_x = 48) run as separate launch
+    groups of one plan:
     every instance matches the oracle, and the batched, per-slice and
     graph-replayed solves, before and after tuning, agree bit for bit with
     the single-instance solves."""
