@@ -17,6 +17,7 @@ batched solve against plain per-slice FP64 Parareal and serial FP64 fine.
 import argparse
 import json
 import os
+import re
 import sys
 import time
 
@@ -136,9 +137,11 @@ def per_config_rates(pr, W, torch, kernel_of):
         ms = ev_time(lambda k: pr.fine_sweep(p, u, [s * p.nf for s in range(p.P)], k, u_out=o), steps)
         lups = p.P * p.npts
         fv = pr.sweep_kernel_variant(p, pr.PR_FP32 if mixed else pr.PR_FP64, p.P, 0)
+        tr, _ = measured_traffic(fv, name)
         out[name] = {"glups": round(lups / ms / 1e6, 1), "gbs": round(lups * 2 * es / ms / 1e6, 1),
                      "frac": round(lups * 2 * es / ms / 1e6 / HBM_PEAK_GBS, 4),
-                     "launch_us": round(ms * 1e3, 1), "kernel": "%s (%s)" % (kernel_of(fv), fv)}
+                     "launch_us": round(ms * 1e3, 1), "kernel": "%s (%s)" % (kernel_of(fv), fv),
+                     "traffic": tr, "traffic_over_algorithmic": None if tr is None else round(tr / (lups * 2 * es), 3)}
         del u, o
         torch.cuda.empty_cache()
     # the paper's own setup (Section 3.1): fourth-order F on 128^3 FP64, all
@@ -149,9 +152,12 @@ def per_config_rates(pr, W, torch, kernel_of):
     ms = ev_time(lambda k: pr.fine_sweep(pp, u, [s * pp.nf for s in range(pp.P)], k, u_out=o), 32)
     lups = pp.P * pp.npts
     fv = pr.sweep_kernel_variant(pp, pr.PR_FP64, pp.P, 0)
+    tr, _ = measured_traffic(fv, "paper_setup_order4_fp64")
     out["paper_setup_order4_fp64"] = {"glups": round(lups / ms / 1e6, 1), "gbs": round(lups * 16 / ms / 1e6, 1),
                                       "frac": round(lups * 16 / ms / 1e6 / HBM_PEAK_GBS, 4),
-                                      "launch_us": round(ms * 1e3, 1), "kernel": "%s (%s)" % (kernel_of(fv), fv)}
+                                      "launch_us": round(ms * 1e3, 1), "kernel": "%s (%s)" % (kernel_of(fv), fv),
+                                      "traffic": tr,
+                                      "traffic_over_algorithmic": None if tr is None else round(tr / (lups * 16), 3)}
     del u, o
     torch.cuda.empty_cache()
     insts = W.batched_config(64)
@@ -174,13 +180,19 @@ def per_config_rates(pr, W, torch, kernel_of):
             best = min(best, plan.timings()["fine_ms"])
         rates[label] = (best, plan)
     fine_ms, plan = rates["tuned"]
+    # whole-row variants name their row width; each group of the workload is one grid size
+    grid_of = {v: int(re.search(r"_x(\d+)_", v).group(1)) for v, _, _ in plan.fine_groups()
+               if re.search(r"_x(\d+)_", v)}
     out["c4_batched_64"] = {"glups": round(lups / fine_ms / 1e6, 1),
                             "gbs": round(lups * 8 / fine_ms / 1e6, 1),
                             "frac": round(lups * 8 / fine_ms / 1e6 / HBM_PEAK_GBS, 4),
                             "tuned": True, "tuning_s": round(tune_s, 2),
                             "glups_builtin_choice": round(lups / rates["builtin"][0] / 1e6, 1),
                             "kernel": "%s (%s)" % (kernel_of(plan.kernel_variants()[0]), plan.kernel_variants()[0]),
-                            "launch_groups": [{"variant": v, "blocks_per_cu": b, "instances": n}
+                            "launch_groups": [{"variant": v, "blocks_per_cu": b, "instances": n,
+                                               "traffic_per_step": measured_traffic(
+                                                   v, "c4_batched_64:%d^3 group" % grid_of[v])[0]
+                                               if v in grid_of else None}
                                               for v, b, n in plan.fine_groups()]}
     del rates, plan, u0s
     torch.cuda.empty_cache()
