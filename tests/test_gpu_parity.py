@@ -136,6 +136,7 @@ def test_fine_variants_bitwise_identical(pr, dtype, order):
 @pytest.mark.parametrize("dtype", [1, 2])
 @pytest.mark.parametrize("n3,order", [((128, 52, 21), 2), ((64, 37, 19), 2), ((256, 20, 9), 2), ((128, 8, 5), 2),
                                       ((96, 52, 21), 2), ((48, 37, 19), 2), ((48, 8, 5), 2), ((96, 100, 6), 2),
+                                      ((32, 29, 13), 2), ((32, 8, 5), 2), ((64, 70, 9), 2),
                                       ((128, 52, 21), 4), ((128, 8, 5), 4), ((128, 19, 40), 4)])
 def test_fine_whole_row_variants_bitwise_identical(pr, dtype, n3, order):
     """The whole-row kernels (x neighbours across the wavefront; for order 4
