@@ -247,10 +247,21 @@ def workload_solves(pr, W, torch, quick=False):
         mode = pr.PR_MODE_MIXED if mixed else pr.PR_MODE_FP64
         plan = pr.Plan([p], mode)
         t = timed(lambda: plan.solve([u0], uT=[uT], want_log=False), reps)
+        batched = grab(uT)
         rec["forms"]["parareal_batched_" + ("fp32_sweeps" if mixed else "fp64")] = {"ms": round(t, 3),
-                                                                                  "result": grab(uT)}
+                                                                                  "result": batched}
         del plan
         torch.cuda.empty_cache()
+        if name in ("c2_128_fp64", "c3_256_mixed"):
+            # the pipelined schedule (Section 2.2.1) in two slice groups
+            plan = pr.Plan([p], mode | pr.PR_MODE_PIPELINED | pr.PR_MODE_PIPELINE_GROUPS(2))
+            t = timed(lambda: plan.solve([u0], uT=[uT], want_log=False), reps)
+            res = grab(uT)
+            rec["forms"]["parareal_batched_pipelined"] = {
+                "ms": round(t, 3), "result": res, "slice_groups": 2,
+                "bitwise_equal_to_batched": bool(np.array_equal(res, batched))}
+            del plan
+            torch.cuda.empty_cache()
         plan = pr.Plan([p], pr.PR_MODE_FP64 | pr.PR_MODE_PER_SLICE)
         t = timed(lambda: plan.solve([u0], uT=[uT], want_log=False), reps)
         rec["forms"]["parareal_plain_fp64_per_slice"] = {"ms": round(t, 3), "result": grab(uT)}
@@ -666,6 +677,10 @@ def main():
         wl = {}
         for name, rec in solves.items():
             e = {"time_to_solution_ms": {form: r["ms"] for form, r in rec["forms"].items()}}
+            pf = rec["forms"].get("parareal_batched_pipelined")
+            if pf is not None:
+                e["pipelined"] = {"slice_groups": pf["slice_groups"],
+                                  "bitwise_equal_to_batched": pf["bitwise_equal_to_batched"]}
             if cpu is not None and name in cpu["per_workload"]:
                 c = cpu["per_workload"][name]
                 for key in ("reference", "accuracy_vs_fp64_parareal", "accuracy_vs_fp64_serial_fine"):

@@ -64,6 +64,17 @@ extern "C" {
 #define PR_MODE_PER_SLICE 16  /* OR-able: launch F slice by slice instead of batched */
 #define PR_MODE_GRAPH     32  /* OR-able: record the solve once in a HIP graph and replay it */
 #define PR_MODE_TIMED     64  /* OR-able: time the F and G phases with HIP events (eager launches) */
+/* OR-able: the pipelined schedule of Section 2.2.1 on one device.  The slices
+ * are cut into consecutive slice groups; F of group g in iteration k starts as
+ * soon as iteration k-1's coarse chain has corrected every slice of g, on
+ * streams owned by the plan, while the chain goes on with later groups on the
+ * solve's stream, and iteration k's chain enters group g once that F is done.
+ * Results are bitwise those of the phase-by-phase schedule.  Not with
+ * PR_MODE_PER_SLICE or PR_EARLY_STOP (which reads each iteration's norms on
+ * the host before the next F may start). */
+#define PR_MODE_PIPELINED 128
+/* slice groups of PR_MODE_PIPELINED (1..255; 0 or absent: 2), OR-ed into mode */
+#define PR_MODE_PIPELINE_GROUPS(g) ((int32_t)(g) << 16)
 
 /* problem flags */
 #define PR_NU_FROZEN      1u  /* nu(t_j) for all RK4 stages of step j */
@@ -226,7 +237,8 @@ int pr_copy_probe(const void *src, void *dst, size_t bytes, int32_t variant, int
  *   probs   HOST array [ninst] of problems (each with its own grid, a, nu,
  *           step counts and P; K and flags must be equal across instances)
  *   mode    PR_MODE_FP64 or PR_MODE_MIXED, optionally | PR_MODE_PER_SLICE,
- *           | PR_MODE_GRAPH
+ *           | PR_MODE_GRAPH, | PR_MODE_TIMED, | PR_MODE_PIPELINED (with
+ *           | PR_MODE_PIPELINE_GROUPS(g))
  *   ws      device workspace of pr_plan_workspace_bytes(probs, ninst, mode)
  *           bytes; owned by the caller, must outlive the plan
  * pr_plan_create validates everything (including stability unless
@@ -279,7 +291,11 @@ int pr_plan_fine_groups(const pr_plan *plan, int32_t max, int32_t *count, int32_
  * (HOST out[6]): {F ms, G-chain ms (coarse sweeps and corrections), start-up
  * coarse ms, number of fused F step launches, number of G launches, total ms}.
  * F time is measured from before the first to after the last step launch of
- * each iteration, so it includes launch gaps.
+ * each iteration, so it includes launch gaps.  Under PR_MODE_PIPELINED the
+ * phases overlap: F time sums, over iterations and slice groups, the span of
+ * the group's step launches on the F streams, and G-chain time sums, per
+ * iteration, the span from the chain's entry into the first slice group to
+ * its end.
  */
 int pr_plan_timings(const pr_plan *plan, double *out6);
 

@@ -14,7 +14,8 @@ import os
 
 from . import _lib as L
 from ._lib import (PR_ALLOW_UNSTABLE, PR_COARSEN_G, PR_CUBIC_INTERP, PR_EARLY_STOP, PR_FP32,  # noqa: F401
-                   PR_FP64, PR_MODE_FP64, PR_MODE_GRAPH, PR_MODE_MIXED, PR_MODE_PER_SLICE, PR_MODE_TIMED,
+                   PR_FP64, PR_MODE_FP64, PR_MODE_GRAPH, PR_MODE_MIXED, PR_MODE_PER_SLICE,
+                   PR_MODE_PIPELINE_GROUPS, PR_MODE_PIPELINED, PR_MODE_TIMED,
                    PR_NU_FROZEN, PR_SKIP_CONVERGED, PrError, check, lib, to_struct)
 
 __all__ = ["fine_sweep", "coarse_sweep", "parareal_update", "defect_norm", "restrict", "prolong",

@@ -12,6 +12,13 @@ LIB_PATH = os.path.join(HERE, "libpr.so")
 PR_OK, PR_EINVAL, PR_EUNSTABLE, PR_ENOMEM, PR_EDEVICE, PR_EUNSUPPORTED, PR_ENONFINITE = 0, -1, -2, -3, -4, -5, -6
 PR_FP32, PR_FP64 = 1, 2
 PR_MODE_FP64, PR_MODE_MIXED, PR_MODE_PER_SLICE, PR_MODE_GRAPH, PR_MODE_TIMED = 0, 1, 16, 32, 64
+PR_MODE_PIPELINED = 128
+
+
+def PR_MODE_PIPELINE_GROUPS(g):
+    """slice groups of PR_MODE_PIPELINED, OR-ed into a plan mode (1..255)"""
+    return int(g) << 16
+
 PR_DEFECT_STATIC_MAX_BATCH = 64
 PR_NU_FROZEN, PR_ALLOW_UNSTABLE, PR_EARLY_STOP, PR_SKIP_CONVERGED, PR_COARSEN_G, PR_CUBIC_INTERP = 1, 2, 4, 8, 16, 32
 

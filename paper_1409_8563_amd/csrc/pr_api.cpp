@@ -758,6 +758,24 @@ struct pr_plan {
     hipEvent_t fork_ev = nullptr;
     std::vector<hipEvent_t> join_ev;
 
+    // Pipelined schedule (PR_MODE_PIPELINED): slices [pg_begin[g],
+    // pg_begin[g+1]) form slice group g.  F of (k, g) runs, group by group, on
+    // fstream[f] for each launch group f (table ptab[(k*npg + g)*nfg + f]);
+    // events: ready[k*npg + g] (on the solve's stream: F of (k, g) may start),
+    // first[..] and done[..] (on the F streams, per table: its first step,
+    // which reads U^k_n, has run; all its steps have run), and per table the
+    // timing pair tbeg/tend (PR_MODE_TIMED only).
+    bool pipe = false;
+    int npg = 0;
+    std::vector<int> pg_begin;
+    struct PipeTab {
+        int off = 0, cnt = 0;
+        std::vector<int> active;
+    };
+    std::vector<PipeTab> ptab;
+    std::vector<hipStream_t> fstream;
+    std::vector<hipEvent_t> ready, first, done, tbeg, tend;
+
     // device tables
     ItemDesc *fine_tab = nullptr;       // per k and group: the group's items (batched layout)
     ItemDesc *slice_tab = nullptr;      // per-slice layout: all (i, n), block_begin = 0
@@ -844,7 +862,9 @@ size_t plan_layout(const pr_problem *probs, int ninst, int mode, char *base, pr_
         if (plan) plan->inst.push_back(in);
     }
     const int Kt = std::max(K, 1);
-    char *fine_tab = take((size_t)Kt * sumP * sizeof(ItemDesc));
+    // the pipelined schedule keeps a second set of F tables, cut by slice group
+    const size_t fine_sets = (mode & PR_MODE_PIPELINED) ? 2 : 1;
+    char *fine_tab = take(fine_sets * Kt * sumP * sizeof(ItemDesc));
     char *slice_tab = take((size_t)sumP * sizeof(ItemDesc));
     char *coarse_tab = take((size_t)2 * Pmax * ninst * sizeof(ItemDesc));
     char *rst_tab = take((size_t)Pmax * ninst * sizeof(ItemDesc));
@@ -883,8 +903,16 @@ int validate_plan_args(const pr_problem *probs, int ninst, int mode)
 {
     if (!probs) return fail(PR_EINVAL, "probs is NULL");
     if (ninst < 1) return fail(PR_EINVAL, "ninst must be >= 1");
-    if (mode & ~(PR_MODE_MIXED | PR_MODE_PER_SLICE | PR_MODE_GRAPH | PR_MODE_TIMED))
+    if (mode & ~(PR_MODE_MIXED | PR_MODE_PER_SLICE | PR_MODE_GRAPH | PR_MODE_TIMED | PR_MODE_PIPELINED |
+                 PR_MODE_PIPELINE_GROUPS(255)))
         return fail(PR_EINVAL, "unknown mode bits 0x%x", mode);
+    if ((mode & PR_MODE_PIPELINE_GROUPS(255)) && !(mode & PR_MODE_PIPELINED))
+        return fail(PR_EINVAL, "slice groups given without PR_MODE_PIPELINED");
+    if ((mode & PR_MODE_PIPELINED) && (mode & PR_MODE_PER_SLICE))
+        return fail(PR_EINVAL, "PR_MODE_PIPELINED does not combine with PR_MODE_PER_SLICE");
+    if ((mode & PR_MODE_PIPELINED) && (probs[0].flags & PR_EARLY_STOP))
+        return fail(PR_EINVAL, "PR_MODE_PIPELINED does not combine with PR_EARLY_STOP (the norms of iteration k "
+                               "are read on the host before F of iteration k+1 may start)");
     for (int i = 0; i < ninst; ++i) {
         int rc = validate_problem(&probs[i], true);
         if (rc) {
@@ -970,27 +998,40 @@ int build_tables(pr_plan *pl)
         g.cnt.assign(std::max(K, 1), 0);
         g.active.assign(std::max(K, 1), {});
     }
-    for (int k = 0; k < K; ++k)
-        for (auto &g : pl->fgroups) {
-            std::vector<ItemDesc> items;
-            for (int i : g.insts)
-                for (int n = (pl->skip ? k : 0); n < pl->inst[i].P; ++n) items.push_back(fine_item(i, n));
-            std::stable_sort(items.begin(), items.end(),
-                             [](const ItemDesc &a, const ItemDesc &b) { return a.nsteps > b.nsteps; });
-            layout(items, fine_info(g.v), g.v == 1, 2, 8, g.bpc, pr::fine_occupancy(g.v));
-            const int maxsteps = items.empty() ? 0 : items[0].nsteps;
-            std::vector<int> act(maxsteps, 0);
-            for (int j = 0; j < maxsteps; ++j) {
-                int blocks = 0;
-                for (auto &it : items)
-                    if (it.nsteps > j) blocks = it.block_begin + it.nblocks;
-                act[j] = blocks;
-            }
-            g.active[k] = act;
-            g.off[k] = (int)all.size();
-            g.cnt[k] = (int)items.size();
-            all.insert(all.end(), items.begin(), items.end());
+    // the items of launch group g's slices n in [nlo, nhi) of every instance,
+    // laid out and appended to `all`; returns (offset, count, active blocks)
+    auto fine_table = [&](const pr_plan::FineGroup &g, int nlo, int nhi, int &off, int &cnt, std::vector<int> &act) {
+        std::vector<ItemDesc> items;
+        for (int i : g.insts)
+            for (int n = nlo; n < std::min(nhi, pl->inst[i].P); ++n) items.push_back(fine_item(i, n));
+        std::stable_sort(items.begin(), items.end(),
+                         [](const ItemDesc &a, const ItemDesc &b) { return a.nsteps > b.nsteps; });
+        layout(items, fine_info(g.v), g.v == 1, 2, 8, g.bpc, pr::fine_occupancy(g.v));
+        const int maxsteps = items.empty() ? 0 : items[0].nsteps;
+        act.assign(maxsteps, 0);
+        for (int j = 0; j < maxsteps; ++j) {
+            int blocks = 0;
+            for (auto &it : items)
+                if (it.nsteps > j) blocks = it.block_begin + it.nblocks;
+            act[j] = blocks;
         }
+        off = (int)all.size();
+        cnt = (int)items.size();
+        all.insert(all.end(), items.begin(), items.end());
+    };
+    for (int k = 0; k < K; ++k)
+        for (auto &g : pl->fgroups) fine_table(g, pl->skip ? k : 0, pl->Pmax, g.off[k], g.cnt[k], g.active[k]);
+    if (pl->pipe) {
+        const int nfg = (int)pl->fgroups.size();
+        pl->ptab.assign((size_t)std::max(K, 1) * pl->npg * nfg, {});
+        for (int k = 0; k < K; ++k)
+            for (int q = 0; q < pl->npg; ++q)
+                for (int f = 0; f < nfg; ++f) {
+                    pr_plan::PipeTab &t = pl->ptab[((size_t)k * pl->npg + q) * nfg + f];
+                    const int nlo = std::max(pl->pg_begin[q], pl->skip ? k : 0);
+                    fine_table(pl->fgroups[f], nlo, pl->pg_begin[q + 1], t.off, t.cnt, t.active);
+                }
+    }
     int rc = upload(pl->fine_tab, all);
     if (rc) return rc;
 
@@ -1120,20 +1161,28 @@ int build_tables(pr_plan *pl)
     return upload(pl->pt_final, fin);
 }
 
+// Start-up coarse run at slice n (after U_n is in place): U_{n+1} = G(U_n).
+int enqueue_init_slice(pr_plan *pl, int n, hipStream_t s)
+{
+    const int ninst = pl->ninst, Pmax = pl->Pmax;
+    const int cnt = pl->coarse_cnt[n];
+    if (!cnt) return PR_OK;
+    const ItemDesc *tab = pl->coarse_tab + (size_t)(0 * Pmax + n) * ninst;
+    if (pl->coarsen) HIPCHK(pr::launch_restrict(pl->dtype, pl->rst_tab + (size_t)n * ninst, cnt, s));
+    for (int c = 0; c < pl->coarse_nch[n]; ++c)
+        HIPCHK(pr::launch_coarse_chunk(pl->coarse_v, pl->dtype, tab, cnt, pl->coarse_blocks[n], c, s));
+    if (pl->coarsen)
+        HIPCHK(pr::launch_prolong(pl->dtype, pl->iorder, pl->pro_tab + (size_t)(0 * Pmax + n) * ninst, cnt, s));
+    HIPCHK(pr::launch_pointwise(pr::kOpAssign, pl->dtype, pl->pt_assign + (size_t)n * ninst, cnt, false, s));
+    return PR_OK;
+}
+
 // Enqueue the start-up coarse run of Algorithm 1 (after U_0 is in place).
 int enqueue_init(pr_plan *pl, hipStream_t s)
 {
-    const int ninst = pl->ninst, Pmax = pl->Pmax;
-    for (int n = 0; n < Pmax; ++n) {
-        const int cnt = pl->coarse_cnt[n];
-        if (!cnt) continue;
-        const ItemDesc *tab = pl->coarse_tab + (size_t)(0 * Pmax + n) * ninst;
-        if (pl->coarsen) HIPCHK(pr::launch_restrict(pl->dtype, pl->rst_tab + (size_t)n * ninst, cnt, s));
-        for (int c = 0; c < pl->coarse_nch[n]; ++c)
-            HIPCHK(pr::launch_coarse_chunk(pl->coarse_v, pl->dtype, tab, cnt, pl->coarse_blocks[n], c, s));
-        if (pl->coarsen)
-            HIPCHK(pr::launch_prolong(pl->dtype, pl->iorder, pl->pro_tab + (size_t)(0 * Pmax + n) * ninst, cnt, s));
-        HIPCHK(pr::launch_pointwise(pr::kOpAssign, pl->dtype, pl->pt_assign + (size_t)n * ninst, cnt, false, s));
+    for (int n = 0; n < pl->Pmax; ++n) {
+        int rc = enqueue_init_slice(pl, n, s);
+        if (rc) return rc;
     }
     return PR_OK;
 }
@@ -1176,40 +1225,56 @@ int enqueue_fine(pr_plan *pl, int k, hipStream_t s)
 
 namespace {
 
-int enqueue_iteration(pr_plan *pl, int k, hipStream_t s, bool with_ref)
+// Iteration k's coarse chain at slice n (Algorithm 1): G of U^{k+1}_n, then
+// the correction U^{k+1}_{n+1} = F(U^k_n) + G(U^{k+1}_n) - G(U^k_n).
+int enqueue_chain_slice(pr_plan *pl, int k, int n, hipStream_t s)
 {
     const int ninst = pl->ninst, Pmax = pl->Pmax;
     const int par = k & 1;
+    const int cnt = pl->coarse_cnt[n];
+    if (!cnt) return PR_OK;
+    if (pl->skip && n == k) {
+        // G_n(U^{k+1}_n) would equal G_old bitwise: U^{k+1}_{n+1} = F + 0
+        HIPCHK(pr::launch_pointwise(pr::kOpCorrect, pl->dtype, pl->pt_skip + ((size_t)par * Pmax + n) * ninst, cnt,
+                                    true, s));
+        return PR_OK;
+    }
+    const int cpar = 1 - par;  // G_new goes to Gold[1 - k%2]
+    const ItemDesc *tab = pl->coarse_tab + ((size_t)cpar * Pmax + n) * ninst;
+    if (pl->coarsen) HIPCHK(pr::launch_restrict(pl->dtype, pl->rst_tab + (size_t)n * ninst, cnt, s));
+    for (int c = 0; c < pl->coarse_nch[n]; ++c)
+        HIPCHK(pr::launch_coarse_chunk(pl->coarse_v, pl->dtype, tab, cnt, pl->coarse_blocks[cpar * Pmax + n], c, s));
+    if (pl->coarsen)
+        HIPCHK(pr::launch_prolong(pl->dtype, pl->iorder, pl->pro_tab + ((size_t)cpar * Pmax + n) * ninst, cnt, s));
+    HIPCHK(pr::launch_pointwise(pr::kOpCorrect, pl->dtype, pl->pt_corr + ((size_t)par * Pmax + n) * ninst, cnt, true,
+                                s));
+    return PR_OK;
+}
+
+// The norms that close iteration k: per-slice inter-iterate finals, and d^k
+// against the reference.
+int enqueue_norms(pr_plan *pl, int k, hipStream_t s, bool with_ref)
+{
+    HIPCHK(pr::launch_defect_final(pl->pt_final + (size_t)k * pl->sumP, pl->sumP, s));
+    if (with_ref) {
+        HIPCHK(pr::launch_defect_partials(PR_FP64, PR_FP64, pl->io_ref + (size_t)k * pl->ninst, pl->ninst, s));
+        HIPCHK(pr::launch_defect_final(pl->io_ref + (size_t)k * pl->ninst, pl->ninst, s));
+    }
+    return PR_OK;
+}
+
+int enqueue_iteration(pr_plan *pl, int k, hipStream_t s, bool with_ref)
+{
     if (pl->timed) HIPCHK(hipEventRecord(pl->ev[2 + 3 * k], s));
     int rc = enqueue_fine(pl, k, s);
     if (rc) return rc;
     if (pl->timed) HIPCHK(hipEventRecord(pl->ev[3 + 3 * k], s));
-    const int nstart = pl->skip ? k : 0;
-    for (int n = nstart; n < Pmax; ++n) {
-        const int cnt = pl->coarse_cnt[n];
-        if (!cnt) continue;
-        if (pl->skip && n == k) {
-            // G_n(U^{k+1}_n) would equal G_old bitwise: U^{k+1}_{n+1} = F + 0
-            HIPCHK(pr::launch_pointwise(pr::kOpCorrect, pl->dtype, pl->pt_skip + ((size_t)par * Pmax + n) * ninst, cnt,
-                                        true, s));
-            continue;
-        }
-        const int cpar = 1 - par;  // G_new goes to Gold[1 - k%2]
-        const ItemDesc *tab = pl->coarse_tab + ((size_t)cpar * Pmax + n) * ninst;
-        if (pl->coarsen) HIPCHK(pr::launch_restrict(pl->dtype, pl->rst_tab + (size_t)n * ninst, cnt, s));
-        for (int c = 0; c < pl->coarse_nch[n]; ++c)
-            HIPCHK(pr::launch_coarse_chunk(pl->coarse_v, pl->dtype, tab, cnt, pl->coarse_blocks[cpar * Pmax + n], c, s));
-        if (pl->coarsen)
-            HIPCHK(pr::launch_prolong(pl->dtype, pl->iorder, pl->pro_tab + ((size_t)cpar * Pmax + n) * ninst, cnt,
-                                      s));
-        HIPCHK(pr::launch_pointwise(pr::kOpCorrect, pl->dtype, pl->pt_corr + ((size_t)par * Pmax + n) * ninst, cnt,
-                                    true, s));
+    for (int n = pl->skip ? k : 0; n < pl->Pmax; ++n) {
+        rc = enqueue_chain_slice(pl, k, n, s);
+        if (rc) return rc;
     }
-    HIPCHK(pr::launch_defect_final(pl->pt_final + (size_t)k * pl->sumP, pl->sumP, s));
-    if (with_ref) {
-        HIPCHK(pr::launch_defect_partials(PR_FP64, PR_FP64, pl->io_ref + (size_t)k * ninst, ninst, s));
-        HIPCHK(pr::launch_defect_final(pl->io_ref + (size_t)k * ninst, ninst, s));
-    }
+    rc = enqueue_norms(pl, k, s, with_ref);
+    if (rc) return rc;
     if (pl->timed) HIPCHK(hipEventRecord(pl->ev[4 + 3 * k], s));
     return PR_OK;
 }
@@ -1231,8 +1296,112 @@ int enqueue_tail(pr_plan *pl, hipStream_t s)
     return PR_OK;
 }
 
+// F of iteration k on slice group q: for every launch group with slices in
+// q, on that group's F stream, after the chain has made the group ready.
+int enqueue_pipe_fine(pr_plan *pl, int k, int q)
+{
+    const int nfg = (int)pl->fgroups.size();
+    const size_t e = (size_t)k * pl->npg + q;
+    for (int f = 0; f < nfg; ++f) {
+        const size_t t = e * nfg + f;
+        const pr_plan::PipeTab &tb = pl->ptab[t];
+        if (!tb.cnt) continue;
+        const auto &gr = pl->fgroups[f];
+        hipStream_t fs = pl->fstream[f];
+        HIPCHK(hipStreamWaitEvent(fs, pl->ready[e], 0));
+        if (pl->timed) HIPCHK(hipEventRecord(pl->tbeg[t], fs));
+        for (int j = 0; j < (int)tb.active.size(); ++j) {
+            HIPCHK(pr::launch_fine_step(gr.v, pl->dtype, pl->probs[0].fine_order, pl->fine_tab + tb.off, tb.cnt,
+                                        tb.active[j], j, fs));
+            if (j == 0) HIPCHK(hipEventRecord(pl->first[t], fs));
+        }
+        if (pl->timed) HIPCHK(hipEventRecord(pl->tend[t], fs));
+        HIPCHK(hipEventRecord(pl->done[t], fs));
+    }
+    return PR_OK;
+}
+
+// The solve's stream waits until F of (k, q) has run all its steps (which =
+// done) or its first step (which = first), for every launch group in q.
+int wait_pipe_fine(pr_plan *pl, int k, int q, bool first, hipStream_t s)
+{
+    const int nfg = (int)pl->fgroups.size();
+    for (int f = 0; f < nfg; ++f) {
+        const size_t t = ((size_t)k * pl->npg + q) * nfg + f;
+        if (pl->ptab[t].cnt) HIPCHK(hipStreamWaitEvent(s, first ? pl->first[t] : pl->done[t], 0));
+    }
+    return PR_OK;
+}
+
+// The pipelined schedule (Section 2.2.1, Algorithm 1 with each slice's F
+// started as soon as its input is final).  Dependencies, per slice group q:
+//   F(k, q) after the chain of iteration k-1 has left q (U^k_n of q final, and
+//     F^{k-1}_n of q consumed by its corrections; for k = 0, after the
+//     start-up run has set U^0_n of q);
+//   the chain of iteration k enters q after F(k, q) is done;
+//   its correction at the last slice of q, which writes U^{k+1} of the first
+//     slice of q+1, waits until F(k, q+1) has run its first step (the only
+//     step that reads U^k there).
+// Every buffer is then read and written in the order of the phase-by-phase
+// schedule, so the results are bitwise the same.
+int enqueue_pipelined(pr_plan *pl, hipStream_t s, bool with_ref)
+{
+    const int npg = pl->npg, K = pl->K, Pmax = pl->Pmax;
+    const std::vector<int> &b = pl->pg_begin;
+    int rc;
+    HIPCHK(pr::launch_pointwise(pr::kOpCopy64, pl->dtype, pl->io_u0, pl->ninst, false, s));
+    if (pl->timed) HIPCHK(hipEventRecord(pl->ev[0], s));
+    // start-up run: group q is ready once U^0 of its last slice is set, i.e.
+    // after slice b[q+1]-2 (U_0 is set before the run)
+    int q = 0;
+    for (int n = -1; n < Pmax; ++n) {
+        if (n >= 0) {
+            rc = enqueue_init_slice(pl, n, s);
+            if (rc) return rc;
+        }
+        for (; q < npg && b[q + 1] - 2 <= n; ++q)
+            if (K > 0) HIPCHK(hipEventRecord(pl->ready[q], s));
+    }
+    if (pl->timed) HIPCHK(hipEventRecord(pl->ev[1], s));
+    if (K > 0) {
+        rc = enqueue_pipe_fine(pl, 0, 0);
+        if (rc) return rc;
+    }
+    for (int k = 0; k < K; ++k) {
+        const int nstart = pl->skip ? k : 0;
+        for (q = 0; q < npg; ++q) {
+            if (q + 1 < npg) {
+                rc = enqueue_pipe_fine(pl, k, q + 1);
+                if (rc) return rc;
+            }
+            if (pl->timed && q == 0) HIPCHK(hipEventRecord(pl->ev[2 + 3 * k], s));
+            rc = wait_pipe_fine(pl, k, q, false, s);
+            if (rc) return rc;
+            if (pl->timed && q == 0) HIPCHK(hipEventRecord(pl->ev[3 + 3 * k], s));
+            for (int n = std::max(b[q], nstart); n < b[q + 1]; ++n) {
+                if (n == b[q + 1] - 1 && q + 1 < npg) {
+                    rc = wait_pipe_fine(pl, k, q + 1, true, s);
+                    if (rc) return rc;
+                }
+                rc = enqueue_chain_slice(pl, k, n, s);
+                if (rc) return rc;
+            }
+            if (k + 1 < K) HIPCHK(hipEventRecord(pl->ready[(size_t)(k + 1) * npg + q], s));
+        }
+        rc = enqueue_norms(pl, k, s, with_ref);
+        if (rc) return rc;
+        if (pl->timed) HIPCHK(hipEventRecord(pl->ev[4 + 3 * k], s));
+        if (k + 1 < K) {
+            rc = enqueue_pipe_fine(pl, k + 1, 0);
+            if (rc) return rc;
+        }
+    }
+    return enqueue_tail(pl, s);
+}
+
 int enqueue_all(pr_plan *pl, hipStream_t s, bool with_ref)
 {
+    if (pl->pipe) return enqueue_pipelined(pl, s, with_ref);
     int rc = enqueue_head(pl, s);
     if (rc) return rc;
     for (int k = 0; k < pl->K; ++k) {
@@ -1246,7 +1415,10 @@ int count_launches(const pr_plan *pl, double *nf, double *ng)
 {
     double f = 0, g = 0;
     for (int k = 0; k < pl->iters_done; ++k) {
-        if (!pl->per_slice) {
+        if (pl->pipe) {
+            const size_t per_k = (size_t)pl->npg * pl->fgroups.size();
+            for (size_t t = 0; t < per_k; ++t) f += (double)pl->ptab[(size_t)k * per_k + t].active.size();
+        } else if (!pl->per_slice) {
             for (const auto &gr : pl->fgroups) f += (double)gr.active[k].size();
         } else {
             for (int i = 0; i < pl->ninst; ++i)
@@ -1619,6 +1791,13 @@ int pr_plan_create(const pr_problem *probs, int32_t ninst, int32_t mode, void *w
     pl->coarse_bpc = cok ? cch.bpc : 0;
 
     plan_layout(probs, ninst, mode, (char *)ws, pl);
+    pl->pipe = (mode & PR_MODE_PIPELINED) != 0;
+    if (pl->pipe) {
+        const int want = (mode >> 16) & 255;
+        pl->npg = std::min(std::max(want > 0 ? want : 2, 1), pl->Pmax);
+        pl->pg_begin.resize(pl->npg + 1);
+        for (int q = 0; q <= pl->npg; ++q) pl->pg_begin[q] = (int)((int64_t)q * pl->Pmax / pl->npg);
+    }
     rc = build_tables(pl);
     if (rc) {
         delete pl;
@@ -1633,6 +1812,33 @@ int pr_plan_create(const pr_problem *probs, int32_t ninst, int32_t mode, void *w
             if (er == hipSuccess) pl->aux.push_back(st);
             if (er == hipSuccess) er = hipEventCreateWithFlags(&e, hipEventDisableTiming);
             if (er == hipSuccess) pl->join_ev.push_back(e);
+        }
+        if (er != hipSuccess) {
+            pr_plan_destroy(pl);
+            return fail(PR_EDEVICE, "stream or event creation failed: %s", hipGetErrorString(er));
+        }
+    }
+    if (pl->pipe) {
+        const size_t nt = pl->ptab.size();
+        hipError_t er = hipSuccess;
+        for (size_t f = 0; f < pl->fgroups.size() && er == hipSuccess; ++f) {
+            hipStream_t st = nullptr;
+            er = hipStreamCreateWithFlags(&st, hipStreamNonBlocking);
+            if (er == hipSuccess) pl->fstream.push_back(st);
+        }
+        auto make = [&](std::vector<hipEvent_t> &v, size_t n, bool timing) {
+            for (size_t i = 0; i < n && er == hipSuccess; ++i) {
+                hipEvent_t e = nullptr;
+                er = timing ? hipEventCreate(&e) : hipEventCreateWithFlags(&e, hipEventDisableTiming);
+                if (er == hipSuccess) v.push_back(e);
+            }
+        };
+        make(pl->ready, (size_t)std::max(pl->K, 1) * pl->npg, false);
+        make(pl->first, nt, false);
+        make(pl->done, nt, false);
+        if (pl->timed) {
+            make(pl->tbeg, nt, true);
+            make(pl->tend, nt, true);
         }
         if (er != hipSuccess) {
             pr_plan_destroy(pl);
@@ -1664,6 +1870,9 @@ void pr_plan_destroy(pr_plan *plan)
     for (auto st : plan->aux) (void)hipStreamDestroy(st);
     for (auto e : plan->join_ev) (void)hipEventDestroy(e);
     if (plan->fork_ev) (void)hipEventDestroy(plan->fork_ev);
+    for (auto st : plan->fstream) (void)hipStreamDestroy(st);
+    for (auto *v : {&plan->ready, &plan->first, &plan->done, &plan->tbeg, &plan->tend})
+        for (auto e : *v) (void)hipEventDestroy(e);
     delete plan;
 }
 
@@ -1847,9 +2056,26 @@ int pr_parareal_solve(pr_plan *pl, const double *const *u0, double *const *uT, c
         double f = 0, g = 0;
         HIPCHK(hipEventElapsedTime(&ms, pl->ev[0], pl->ev[1]));
         pl->timings[2] = ms;
+        const int nfg = (int)pl->fgroups.size();
         for (int k = 0; k < Kd; ++k) {
-            HIPCHK(hipEventElapsedTime(&ms, pl->ev[2 + 3 * k], pl->ev[3 + 3 * k]));
-            f += ms;
+            if (pl->pipe) {
+                // span of each slice group's F over its launch groups' streams
+                for (int q = 0; q < pl->npg; ++q) {
+                    double lo = 1e300, hi = -1e300;
+                    for (int ff = 0; ff < nfg; ++ff) {
+                        const size_t t = ((size_t)k * pl->npg + q) * nfg + ff;
+                        if (!pl->ptab[t].cnt) continue;
+                        HIPCHK(hipEventElapsedTime(&ms, pl->ev[0], pl->tbeg[t]));
+                        lo = std::min(lo, (double)ms);
+                        HIPCHK(hipEventElapsedTime(&ms, pl->ev[0], pl->tend[t]));
+                        hi = std::max(hi, (double)ms);
+                    }
+                    if (hi > lo) f += hi - lo;
+                }
+            } else {
+                HIPCHK(hipEventElapsedTime(&ms, pl->ev[2 + 3 * k], pl->ev[3 + 3 * k]));
+                f += ms;
+            }
             HIPCHK(hipEventElapsedTime(&ms, pl->ev[3 + 3 * k], pl->ev[4 + 3 * k]));
             g += ms;
         }

@@ -151,6 +151,36 @@ def test_plan_validation():
     assert L.lib().pr_plan_create(arr, 1, 0, ctypes.c_void_p(1 << 40), 100, ctypes.byref(h)) == L.PR_ENOMEM
 
 
+def test_pipelined_mode_validation():
+    """The pipelined schedule is a plan mode: it takes a slice-group count,
+    refuses the per-slice F and early stop, and keeps a second set of F
+    tables in the workspace."""
+    L = _lib()
+    good = W.small_problem(n=(16, 16, 16), P=4, K=2)
+
+    def rc_for(q, mode):
+        arr = (L.PrProblem * 1)(L.to_struct(q))
+        h = ctypes.c_void_p()
+        rc = L.lib().pr_plan_create(arr, 1, mode, ctypes.c_void_p(1 << 40), 1 << 50, ctypes.byref(h))
+        return rc, L.last_error()
+
+    pipe = L.PR_MODE_PIPELINED
+    assert rc_for(good, pipe)[0] == L.PR_EDEVICE            # valid: fails only for want of a device
+    assert rc_for(good, pipe | L.PR_MODE_PIPELINE_GROUPS(3) | L.PR_MODE_GRAPH)[0] == L.PR_EDEVICE
+    rc, msg = rc_for(good, L.PR_MODE_PIPELINE_GROUPS(2))
+    assert rc == L.PR_EINVAL and "PR_MODE_PIPELINED" in msg
+    rc, msg = rc_for(good, pipe | L.PR_MODE_PER_SLICE)
+    assert rc == L.PR_EINVAL and "PER_SLICE" in msg
+    early = W.small_problem(n=(16, 16, 16), P=4, K=2)
+    early.flags |= L.PR_EARLY_STOP
+    rc, msg = rc_for(early, pipe)
+    assert rc == L.PR_EINVAL and "EARLY_STOP" in msg
+    arr = (L.PrProblem * 1)(L.to_struct(good))
+    plain = L.lib().pr_plan_workspace_bytes(arr, 1, 0)
+    piped = L.lib().pr_plan_workspace_bytes(arr, 1, pipe)
+    assert piped > plain
+
+
 def test_workspace_sizes():
     """The largest single-instance workload fits in 288 GB of HBM."""
     L = _lib()

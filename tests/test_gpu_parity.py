@@ -338,6 +338,61 @@ def test_parareal_modes_bitwise_identical(pr):
         del scratch
 
 
+@pytest.mark.parametrize("groups", [1, 2, 3, 7])
+def test_pipelined_schedule_bitwise_identical(pr, groups):
+    """The pipelined schedule (F of a slice group starts as soon as the
+    previous iteration's chain has corrected it, while the chain goes on)
+    reads and writes every buffer in the phase-by-phase order: every slice
+    state, the result and the logs are the same bits, in FP64 and mixed
+    precision, with and without skipping converged slices, with the
+    reference defect, timed, and replayed from a recorded graph."""
+    import torch
+    ref_u = None
+    for mode in (pr.PR_MODE_FP64, pr.PR_MODE_MIXED):
+        for flags in (0, W.SKIP_CONVERGED):
+            p = W.small_problem(n=(40, 24, 28), P=7, nf=4, nc=6, K=4, flags=flags)
+            u0 = W.random_field(p.n, 195)
+            if ref_u is None:
+                ref_u = cuda(W.random_field(p.n, 196))
+            say("pipelined: groups", groups, "mode", mode, "flags", flags)
+            base, blog, bstates, _ = _solve(pr, [p], [u0], mode, ref=[ref_u])
+            pm = mode | pr.PR_MODE_PIPELINED | pr.PR_MODE_PIPELINE_GROUPS(groups)
+            for extra in (0, pr.PR_MODE_TIMED):
+                uT, log, states, plan = _solve(pr, [p], [u0], pm | extra, ref=[ref_u])
+                assert np.array_equal(uT[0], base[0]), extra
+                assert np.array_equal(log, blog), extra
+                for n in range(p.P + 1):
+                    assert np.array_equal(states[0][n], bstates[0][n]), (extra, n)
+                if extra:
+                    tm = plan.timings()
+                    assert tm["fine_ms"] > 0 and tm["coarse_chain_ms"] > 0 and tm["total_ms"] > 0, tm
+                    assert tm["fine_launches"] >= p.K * (p.nt_fine // p.P), tm
+            plan = pr.Plan([p], pm | pr.PR_MODE_GRAPH)
+            x = cuda(u0)
+            for rep in range(3):
+                uT, glog = plan.solve([x], ref=[ref_u])
+                scratch = torch.randn(1000, device="cuda").sum()   # eager work between replays
+                torch.cuda.synchronize()
+                assert np.array_equal(host(uT[0]), base[0]), rep
+                assert np.array_equal(glog, blog), rep
+                del scratch
+
+
+def test_pipelined_schedule_other_paths_bitwise(pr):
+    """Pipelined solves of the fourth-order F (two launches per step through
+    scratch fields) and of the coarsened G match their phase-by-phase solves."""
+    cases = [("order 4", W.small_problem(n=(128, 20, 18), P=5, nf=6, nc=4, K=3, order=4, nu0=0.0005)),
+             ("coarsened G", W.small_problem(n=(32, 24, 20), P=6, nf=8, nc=4, K=3, flags=W.COARSEN_G))]
+    for name, p in cases:
+        u0 = W.random_field(p.n, 197)
+        say("pipelined:", name)
+        base, blog, bstates, _ = _solve(pr, [p], [u0], pr.PR_MODE_FP64)
+        uT, log, states, _ = _solve(pr, [p], [u0], pr.PR_MODE_FP64 | pr.PR_MODE_PIPELINED)
+        assert np.array_equal(uT[0], base[0]) and np.array_equal(log, blog), name
+        for n in range(p.P + 1):
+            assert np.array_equal(states[0][n], bstates[0][n]), (name, n)
+
+
 def test_parareal_mixed_against_oracle(pr, orc):
     say("parareal mixed")
     modes = W.draw_modes(np.random.default_rng(200), 8, 4)
@@ -480,8 +535,11 @@ def test_multi_instance_launch_groups(pr, orc):
         # skipping converged slices and early stopping at tol = 0 change no bit
         skip_early = [W.Problem(**{**p.__dict__, "flags": p.flags | W.SKIP_CONVERGED | W.EARLY_STOP})
                       for p in probs]
+        skip_only = [W.Problem(**{**p.__dict__, "flags": p.flags | W.SKIP_CONVERGED}) for p in probs]
+        pipe = pr.PR_MODE_PIPELINED
         for extra, ps in ((0, probs), (pr.PR_MODE_PER_SLICE, probs), (pr.PR_MODE_GRAPH, probs),
-                          (pr.PR_MODE_TIMED, probs), (0, skip_early)):
+                          (pr.PR_MODE_TIMED, probs), (0, skip_early), (pipe, probs),
+                          (pipe | pr.PR_MODE_GRAPH, skip_only), (pipe | pr.PR_MODE_PIPELINE_GROUPS(3), probs)):
             say("launch groups", mode, extra, ps[0].flags)
             plan = pr.Plan(ps, mode | extra)
             groups = plan.fine_groups()
