@@ -218,8 +218,9 @@ def workload_solves(pr, W, torch, quick=False):
     blocking calls after one warm call (one call for the 512^3 workload)."""
     import numpy as np
 
-    def timed(fn, reps):
-        fn()
+    def timed(fn, reps, warm=1):
+        for _ in range(warm):
+            fn()
         torch.cuda.synchronize()
         ts = []
         for _ in range(reps):
@@ -245,11 +246,25 @@ def workload_solves(pr, W, torch, quick=False):
         rec = {"forms": {}}
         uT = torch.empty_like(u0)
         mode = pr.PR_MODE_MIXED if mixed else pr.PR_MODE_FP64
-        plan = pr.Plan([p], mode)
-        t = timed(lambda: plan.solve([u0], uT=[uT], want_log=False), reps)
+        big = name == "c5_512_mixed"
+        # the batched solve replayed from a recorded graph, median of 10 after 3 warm calls (the
+        # 512^3 workload: eager, one call after one warm call); plan creation (workspace allocation,
+        # tables) and the first call (which records the graph) are timed on their own
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        plan = pr.Plan([p], mode | (0 if big else pr.PR_MODE_GRAPH))
+        torch.cuda.synchronize()
+        t_create = (time.perf_counter() - t0) * 1e3
+        t0 = time.perf_counter()
+        plan.solve([u0], uT=[uT], want_log=False)
+        torch.cuda.synchronize()
+        t_first = (time.perf_counter() - t0) * 1e3
+        t = timed(lambda: plan.solve([u0], uT=[uT], want_log=False), 1 if big else 10, 1 if big else 3)
         batched = grab(uT)
-        rec["forms"]["parareal_batched_" + ("fp32_sweeps" if mixed else "fp64")] = {"ms": round(t, 3),
-                                                                                  "result": batched}
+        rec["forms"]["parareal_batched_" + ("fp32_sweeps" if mixed else "fp64")] = {
+            "ms": round(t, 3), "result": batched, "plan_create_ms": round(t_create, 1),
+            "first_call_ms": round(t_first, 1),
+            "note": "eager launches" if big else "replayed from a recorded HIP graph; the first call records it"}
         del plan
         torch.cuda.empty_cache()
         if name in ("c2_128_fp64", "c3_256_mixed"):
@@ -677,6 +692,10 @@ def main():
         wl = {}
         for name, rec in solves.items():
             e = {"time_to_solution_ms": {form: r["ms"] for form, r in rec["forms"].items()}}
+            for form, r in rec["forms"].items():
+                extra_t = {k: r[k] for k in ("plan_create_ms", "first_call_ms", "note") if k in r}
+                if extra_t:
+                    e.setdefault("time_to_solution_notes", {})[form] = extra_t
             pf = rec["forms"].get("parareal_batched_pipelined")
             if pf is not None:
                 e["pipelined"] = {"slice_groups": pf["slice_groups"],
