@@ -500,6 +500,9 @@ def main():
     ap.add_argument("--quick", action="store_true", help="leave the 512^3 workload out of that section")
     ap.add_argument("--no-per-config", action="store_true",
                     help="skip the per-workload F kernel rates (all five workloads)")
+    ap.add_argument("--schedules", action="store_true",
+                    help="only run the workload's solve in the phase-by-phase and the pipelined schedule "
+                         "(two calls each, for a kernel trace) and exit")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="run one plain device-to-device copy of this size first (calibrates HBM counters)")
     args = ap.parse_args()
@@ -535,6 +538,19 @@ def main():
 
     u0_np = W.synth_u0(p.n, modes)
     u0 = torch.from_numpy(u0_np).cuda()
+    if args.schedules:
+        uT = torch.empty_like(u0)
+        for name, extra in (("phase-by-phase", 0),
+                            ("pipelined, 2 slice groups", pr.PR_MODE_PIPELINED | pr.PR_MODE_PIPELINE_GROUPS(2))):
+            sp = pr.Plan([p], mode | extra)
+            for rep in range(2):
+                torch.cuda.synchronize()
+                t = time.perf_counter()
+                sp.solve([u0], uT=[uT], want_log=False)
+                torch.cuda.synchronize()
+                log("%s solve %d: %.2f ms" % (name, rep, (time.perf_counter() - t) * 1e3))
+            del sp
+        return
     u0s = u0.to(sdt)
     ufine = torch.empty_like(u0s)
     ufine64 = torch.empty_like(u0)
