@@ -199,23 +199,15 @@ def per_config_rates(pr, W, torch, kernel_of):
     return out
 
 
-N_SAMPLES = 4096
-
-
-def sample_index(npts, seed=7):
-    """Fixed flat indices at which large fields are compared with the reference."""
-    import numpy as np
-    return np.sort(np.random.default_rng(seed).choice(npts, size=min(N_SAMPLES, npts), replace=False))
-
-
 def workload_solves(pr, W, torch, quick=False):
-    """Time-to-solution of every workload on the GPU, in three forms: batched
-    Parareal (FP32 sweeps for the mixed workloads, FP64 otherwise), plain
-    per-slice FP64 Parareal (one F launch per slice and step) and the serial
-    FP64 fine sweep; and the Parareal results (full field for the 32^3
-    workload, fixed sample points elsewhere) for the accuracy check against
-    the FP64 reference computed in the CPU leg.  Times: median of `reps`
-    blocking calls after one warm call (one call for the 512^3 workload)."""
+    """Time-to-solution of every workload on the GPU: batched Parareal (FP32
+    sweeps for the mixed workloads, FP64 otherwise; replayed from a recorded
+    graph, median of 10 calls after 3, except 512^3: eager, one call after
+    one), the pipelined schedule for 128^3 and 256^3, plain per-slice FP64
+    Parareal (one F launch per slice and step) and the serial FP64 fine
+    sweep (median of `reps` calls after one); and every form's result over
+    the whole field for the accuracy check against the FP64 reference
+    computed in the CPU leg."""
     import numpy as np
 
     def timed(fn, reps, warm=1):
@@ -237,11 +229,9 @@ def workload_solves(pr, W, torch, quick=False):
         mixed = W.MIXED[name]
         reps = 1 if name == "c5_512_mixed" else (3 if name == "c3_256_mixed" else 5)
         u0 = torch.from_numpy(W.synth_u0(p.n, modes)).cuda()
-        idx = None if name == "c1_32_fp64" else sample_index(p.npts)
-        idx_t = None if idx is None else torch.from_numpy(idx).cuda()
 
         def grab(u):
-            return (u.view(-1) if idx_t is None else u.view(-1)[idx_t]).cpu().numpy()
+            return u.view(-1).cpu().numpy()   # the whole field
 
         rec = {"forms": {}}
         uT = torch.empty_like(u0)
@@ -284,7 +274,6 @@ def workload_solves(pr, W, torch, quick=False):
         torch.cuda.empty_cache()
         t = timed(lambda: pr.fine_sweep(p, u0, 0, p.nt_fine, u_out=uT), reps)
         rec["forms"]["serial_fine_fp64"] = {"ms": round(t, 3), "result": grab(uT)}
-        rec["idx"] = idx
         out[name] = rec
         del u0, uT
         torch.cuda.empty_cache()
@@ -295,13 +284,10 @@ def workload_solves(pr, W, torch, quick=False):
     probs = [q for q, _ in insts]
     u0s = [torch.from_numpy(W.synth_u0(q.n, m)).cuda() for q, m in insts]
     uTs = [torch.empty_like(u) for u in u0s]
-    idxs = [sample_index(q.npts, seed=11 + i) for i, q in enumerate(probs)]
-    idx_ts = [torch.from_numpy(i).cuda() for i in idxs]
-
     def grab_all():
-        return [u.view(-1)[i].cpu().numpy() for u, i in zip(uTs, idx_ts)]
+        return [u.view(-1).cpu().numpy() for u in uTs]
 
-    rec = {"forms": {}, "idx": idxs}
+    rec = {"forms": {}}
     plan = pr.Plan(probs, pr.PR_MODE_MIXED | pr.PR_MODE_GRAPH)
     plan.autotune()
     t = timed(lambda: plan.solve(u0s, uT=uTs, want_log=False), 3)
@@ -360,7 +346,8 @@ def cpu_leg(p_main, u0_np, solves, budget_s=8.0):
       FP64 reference of the same computation: the grid oracle over the full
       field for the 32^3 workload, elsewhere the oracle's per-Fourier-mode
       model of the same discrete scheme (equal to the grid oracle up to
-      rounding, pinned by the tests) at fixed sample points."""
+      rounding, pinned by the tests) synthesised over the whole field by an
+      inverse FFT."""
     import numpy as np
     import oracle
     from oracle import spectral
@@ -422,20 +409,21 @@ def cpu_leg(p_main, u0_np, solves, budget_s=8.0):
                                             "parareal_s": round(tp, 1), "serial_fine_s": round(p.nt_fine * tf, 1),
                                             "how": how}
         oracle.set_threads(all_threads)
-        if name != "c1_32_fp64":
+        if name != "c1_32_fp64" and name in solves:
             sol = spectral.ModalSolution(p, modes)
-            idx = solves[name]["idx"] if name in solves else None
-            ref = sol.iterate_points(p.K, p.P, idx) if idx is not None else None
-        entry["reference"] = ("grid oracle, full field" if name == "c1_32_fp64" else
-                              "oracle per-mode model, %d sampled points" % N_SAMPLES)
+            ref = sol.iterate_fft(p.K, p.P).ravel()
+        entry["reference"] = ("grid oracle, whole field" if name == "c1_32_fp64" else
+                              "oracle per-mode model synthesised over the whole field (inverse FFT)")
         if name in solves and ref is not None:
             entry["accuracy_vs_fp64_parareal"] = {
                 form: errs(rec["result"], ref) for form, rec in solves[name]["forms"].items()
                 if form.startswith("parareal")}
+            del ref
             fine_ref = (oracle.serial_fine(p, u0).ravel() if name == "c1_32_fp64" else
-                        sol.serial_fine_points(solves[name]["idx"]))
+                        sol.serial_fine_fft().ravel())
             entry["accuracy_vs_fp64_serial_fine"] = {
                 form: errs(rec["result"], fine_ref) for form, rec in solves[name]["forms"].items()}
+            del fine_ref
         per[name] = entry
         log("cpu leg", name, entry)
     if "c4_batched_64" in solves:
@@ -445,8 +433,8 @@ def cpu_leg(p_main, u0_np, solves, budget_s=8.0):
         worst_fine = {}
         for i, (q, modes) in enumerate(insts):
             sol = spectral.ModalSolution(q, modes)
-            r = sol.iterate_points(q.K, q.P, rec["idx"][i])
-            rf = sol.serial_fine_points(rec["idx"][i])
+            r = sol.iterate_fft(q.K, q.P).ravel()
+            rf = sol.serial_fine_fft().ravel()
             for form, fr in rec["forms"].items():
                 for tgt, rr in ((worst, r), (worst_fine, rf)):
                     if tgt is worst and not form.startswith("parareal"):
@@ -456,8 +444,7 @@ def cpu_leg(p_main, u0_np, solves, budget_s=8.0):
                     w["max_abs"] = max(w["max_abs"], e["max_abs"])
                     w["rel_l2"] = max(w["rel_l2"], e["rel_l2"])
         sizes = sorted({q.n[0] for q, _ in insts})
-        c4 = {"reference": "oracle per-mode model per instance, %d sampled points each; worst instance"
-                           % N_SAMPLES,
+        c4 = {"reference": "oracle per-mode model per instance over its whole field (inverse FFT); worst instance",
               "accuracy_vs_fp64_parareal": worst, "accuracy_vs_fp64_serial_fine": worst_fine}
         for th in (1, 8):
             tot_p = tot_s = 0.0

@@ -226,6 +226,10 @@ class ModalSolution:
         s = self.p.P if s is None else s
         return synth_points(self.p.n, self.q, self.c * self.fine[s], idx)
 
+    def serial_fine_fft(self, s=None):
+        s = self.p.P if s is None else s
+        return synth_fft(self.p.n, self.q, self.c * self.fine[s])
+
     def serial_coarse(self, s=None):
         s = self.p.P if s is None else s
         return synth(self.p.n, self.q, self.c * self.coarse[s])
