@@ -449,54 +449,90 @@ bool coarse_applicable(int v, int dtype, const pr_problem &p)
     return vi && vi->dtype == dtype && p.n[0] % vi->nxp == 0 && (vi->rowx == 0 || p.n[0] == vi->rowx);
 }
 
-// Built-in choice (measured on the five workloads and on batches of the
-// uneven workload's grid sizes); batch = fields per launch.
+// Points a fused RK4 kernel computes per output point of the grid's x-y
+// plane, for a tile of tx x ty outputs with a halo of 4 per side.  A 2-D
+// tiled kernel runs every stage on the whole tile.  An x-tiled row kernel
+// (rowx == 0, one x tile per wavefront) runs a stage only in the wavefronts
+// whose rows can still feed an output (stage s: rows s .. EY-1-s), so its y
+// cost is the mean over the four stages of the rows of active wavefronts.
+double fine_tile_cost(const VariantInfo *vi, bool xtiled, const pr_problem &p)
+{
+    const int nx = p.n[0], ny = p.n[1];
+    const double wx = (double)((nx + vi->tx - 1) / vi->tx) * (vi->tx + 8) / nx;
+    const int tiles_y = (ny + vi->ty - 1) / vi->ty;
+    const int ey = vi->ty + 8;
+    if (!xtiled) return wx * ((double)tiles_y * ey / ny);
+    const int waves = vi->threads / 64, rows = ey / waves;
+    double rs = 0;
+    for (int s = 1; s <= 4; ++s)
+        for (int w = 0; w < waves; ++w)
+            if (w * rows + rows - 1 >= s && w * rows < ey - s) rs += rows;
+    return wx * ((double)tiles_y * rs / 4 / ny);
+}
+
+// The candidate of one kernel family that computes the fewest points for
+// the grid.
+int cheapest_tile(const pr_problem &p, std::initializer_list<const char *> names, bool xtiled)
+{
+    int best_v = -1;
+    double best = 1e300;
+    for (const char *nm : names) {
+        const int v = find_fine(nm);
+        const VariantInfo *vi = pr::fine_variant(v);
+        if (!vi || p.n[0] % vi->nxp) continue;
+        const double c = fine_tile_cost(vi, xtiled, p);
+        if (c < best * (1 - 1e-12)) {
+            best = c;
+            best_v = v;
+        }
+    }
+    return best_v;
+}
+
+// Built-in choice (measured on the five workloads, on batches of the uneven
+// workload's grid sizes, and on cubes of other sizes); batch = fields per
+// launch.
 int pick_fine_default(const pr_problem &p, int dtype, int batch)
 {
     const int order = p.fine_order;
     const bool even = p.n[0] % 2 == 0;
     const char *name;
-    if (dtype == PR_FP64)
+    if (dtype == PR_FP64) {
+        // other widths: x-tiled rows (faster than the 2-D tiles on every
+        // cube measured, n = 40 .. 384), the tile height that fits n_y best
+        if (order == 2 && p.n[0] != 128 && p.n[0] != 64 && p.n[0] != 48 && p.n[0] != 32)
+            return cheapest_tile(p, {"rk4x_f64_t56x8_p1x2_w8", "rk4x_f64_t56x16_p1x3_w8"}, true);
         name = order == 4 ? (p.n[0] == 128 ? "rk4h_f64_o4_x128_y8_p2_w16_d1"
                              : even          ? "rk4_f64_o4_t32x16_p2x1"
                                              : "rk4_f64_o4_t24x8_p1x1")
                : p.n[0] == 128 ? "rk4w_f64_x128_y8_p2x1_w16"
                : p.n[0] == 64  ? (batch >= 4 ? "rk4w_f64_x64_y16_p1x2_w12" : "rk4w_f64_x64_y8_p1x2_w8")
                : p.n[0] == 48  ? "rk4s_f64_x48_y24_p3x1_w8"
-               : p.n[0] == 32  ? "rk4s_f64_x32_y32_p2x1_w10"
-                               : "rk4b_f64_t32x32_p1x2_d2";
-    else if (order == 2 && p.n[0] == 64)
+                               : "rk4s_f64_x32_y32_p2x1_w10";
+    } else if (order == 2 && p.n[0] == 64)
         name = batch >= 64 ? "rk4s_f32_x64_y24_p4x1_w8" : "rk4s_f32_x64_y40_p4x1_w12";
     else if (order == 2 && (p.n[0] == 96 || p.n[0] == 48 || p.n[0] == 32))
         name = p.n[0] == 96 ? "rk4s_f32_x96_y24_p6x1_w8"
                : p.n[0] == 48 ? "rk4s_f32_x48_y24_p3x1_w8"
                               : "rk4s_f32_x32_y32_p2x1_w10";
-    else if (order == 2 && even && p.n[0] != 256 && p.n[0] != 128) {
-        // two x points per thread, tiled: the tile that computes the fewest
-        // points per output point of this grid in x and y (halo of 4 per side)
-        static const char *const kTiled[] = {"rk4b_f32_t64x32_p2x2_d2", "rk4b_f32_t64x24_p2x2_d2",
-                                             "rk4b_f32_t48x32_p2x2_d2", "rk4b_f32_t48x24_p2x2_d2"};
-        int best_v = -1;
-        double best = 1e300;
-        for (const char *nm : kTiled) {
-            const int v = find_fine(nm);
-            const VariantInfo *vi = pr::fine_variant(v);
-            if (!vi) continue;
-            const double wx = (double)((p.n[0] + vi->tx - 1) / vi->tx) * (vi->tx + 8) / p.n[0];
-            const double wy = (double)((p.n[1] + vi->ty - 1) / vi->ty) * (vi->ty + 8) / p.n[1];
-            if (wx * wy < best * (1 - 1e-12)) {
-                best = wx * wy;
-                best_v = v;
-            }
-        }
-        return best_v;
+    else if (order == 2 && p.n[0] != 256 && p.n[0] != 128) {
+        // n_x a multiple of 64: the 2-D tile (two x points per thread) that
+        // computes the fewest points, whose 64-wide output tiles cover such
+        // rows exactly (faster than x-tiled rows at 192 and 512, equal at 320
+        // and 384); other widths: x-tiled rows (faster on every cube
+        // measured, n = 40 .. 224)
+        if (p.n[0] % 64 == 0)
+            return cheapest_tile(p,
+                                 {"rk4b_f32_t64x32_p2x2_d2", "rk4b_f32_t64x24_p2x2_d2", "rk4b_f32_t48x32_p2x2_d2",
+                                  "rk4b_f32_t48x24_p2x2_d2"},
+                                 false);
+        name = "rk4x_f32_t56x40_p1x3_w16";
     } else
         name = order == 4 ? (p.n[0] == 128 ? "rk4h_f32_o4_x128_y8_p2_w16"
                              : even          ? "rk4r_f32_o4_t32x16_p2x2_d2"
                                              : "rk4_f32_o4_t32x16_p1x2")
                : p.n[0] == 256 ? "rk4w_f32_x256_y8_p4x2_w8"
-               : p.n[0] == 128 ? (batch >= 4 ? "rk4w_f32_x128_y16_p2x2_w12" : "rk4w_f32_x128_y8_p2x2_w8")
-                               : "rk4b_f32_t32x32_p1x4_d2";
+                               : (batch >= 4 ? "rk4w_f32_x128_y16_p2x2_w12" : "rk4w_f32_x128_y8_p2x2_w8");
     return find_fine(name);
 }
 

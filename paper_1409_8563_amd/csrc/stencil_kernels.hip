@@ -774,17 +774,20 @@ __device__ __forceinline__ double wave_rot(double v)
     return __builtin_bit_cast(double, ((long long)hi << 32) | (unsigned int)lo);
 }
 
-template <typename T, int NXP, int NY, int NW, int PD, int SEG>
+template <typename T, int NXP, int NY, int NW, int PD, int SEG, int XT = 0>
 __global__ void __launch_bounds__(64 * NW)
     rk4_step_rows(const ItemDesc *__restrict__ items, int nitems, int jstep)
 {
     static_assert(4 % PD == 0, "prefetch depth must divide the unroll");
     static_assert(SEG == 64 || SEG == 16, "a grid row spans a wavefront or a 16-lane DPP row");
+    static_assert(!XT || SEG == 64, "x tiles span a wavefront");
     constexpr int R = 1;
     constexpr int H = 4;
     constexpr int RG = 64 / SEG;          // grid rows side by side in a wavefront
     constexpr int NVW = NW * RG;          // row groups of the block
-    constexpr int NX = SEG * NXP;
+    constexpr int NX = SEG * NXP;         // x extent of a row group (the whole row unless XT)
+    constexpr int HX = XT ? H : 0;        // x halo of an x tile
+    constexpr int TXT = NX - 2 * HX;      // output columns of an x tile
     constexpr int EY = NVW * NY, TY = EY - 2 * H;
     constexpr int L = 4;                  // z-ring length (even: LDS slot = phase parity)
     constexpr int NE = NY == 1 ? 1 : 2;   // exchanged rows per row group: first, last
@@ -793,13 +796,19 @@ __global__ void __launch_bounds__(64 * NW)
 
     const int lb = xcd_remap((int)blockIdx.x, (int)gridDim.x);
     const ItemDesc &it = items[find_item(items, nitems, lb)];
-    if (jstep >= it.nsteps || it.nx != NX) return;
+    if (jstep >= it.nsteps || (!XT && it.nx != NX)) return;
     const int local = lb - it.block_begin;
     if (local < 0 || local >= it.nblocks) return;
 
-    const int ny = it.ny, nz = it.nz;
-    const int tyt = local % it.tiles_y;
-    const int zc = local / it.tiles_y;
+    const int nx = XT ? it.nx : NX, ny = it.ny, nz = it.nz;
+    int txt = 0, rest = local;
+    if constexpr (XT) {
+        txt = local % it.tiles_x;
+        rest = local / it.tiles_x;
+    }
+    const int tyt = rest % it.tiles_y;
+    const int zc = rest / it.tiles_y;
+    const int x0 = txt * TXT;
     const int y0 = tyt * TY;
     const int z0 = zc * it.tz;
     const int zend = min(z0 + it.tz, nz);
@@ -820,10 +829,26 @@ __global__ void __launch_bounds__(64 * NW)
 #pragma unroll
     for (int iy = 0; iy < NY; ++iy) {
         const int ry = ry0 + iy;
-        rowoff[iy] = wrapi(y0 - H + ry, ny) * NX + cx0;
+        rowoff[iy] = wrapi(y0 - H + ry, ny) * nx + (XT ? 0 : cx0);
         rowout[iy] = (ry >= H) && (ry < H + TY) && (y0 + ry - H < ny);
     }
-    const int nxy = NX * ny;
+    // x tiles: the lane's columns, wrapped onto the periodic row, and which
+    // of them are outputs of this tile (inside the halo, and not past n_x in
+    // the last, ragged tile).  A row group's lanes hold consecutive columns,
+    // so the rotated-in x neighbours are right except at the two ends of the
+    // wavefront, whose errors reach at most one column further per stage:
+    // four stages stay inside the 4-column halo.
+    int colx[XT ? NXP : 1];
+    bool colout[XT ? NXP : 1];
+    if constexpr (XT) {
+#pragma unroll
+        for (int ix = 0; ix < NXP; ++ix) {
+            const int c = cx0 + ix;
+            colx[ix] = wrapi(x0 - HX + c, nx);
+            colout[ix] = (c >= HX) && (c < HX + TXT) && (x0 + c - HX < nx);
+        }
+    }
+    const int nxy = nx * ny;
     // stage s (1..4) can feed an output point only on rows s .. EY-1-s; a
     // wavefront runs a stage if any of its rows needs it
     const int wr0 = wv * RG * NY;
@@ -853,7 +878,14 @@ __global__ void __launch_bounds__(64 * NW)
     auto load_plane = [&](int p, T(&dstp)[NY][NXP]) {
         const T *base = src + (size_t)wrapi(p, nz) * nxy;
 #pragma unroll
-        for (int iy = 0; iy < NY; ++iy) gld_row<T, NXP>(base + rowoff[iy], dstp[iy]);
+        for (int iy = 0; iy < NY; ++iy) {
+            if constexpr (XT) {
+#pragma unroll
+                for (int ix = 0; ix < NXP; ++ix) dstp[iy][ix] = *(const PR_GLOBAL T *)(base + rowoff[iy] + colx[ix]);
+            } else {
+                gld_row<T, NXP>(base + rowoff[iy], dstp[iy]);
+            }
+        }
     };
 
     // first and last row of this row group's values of a plane -> LDS
@@ -968,7 +1000,14 @@ __global__ void __launch_bounds__(64 * NW)
                     T v[NXP];
 #pragma unroll
                     for (int ix = 0; ix < NXP; ++ix) v[ix] = fmaT(kc.b4, S[iy][ix], ac[slot<L>(M, 4)][iy][ix]);
-                    gst_nt_row<T, NXP>(obase + rowoff[iy], v);
+                    if constexpr (XT) {
+#pragma unroll
+                        for (int ix = 0; ix < NXP; ++ix)
+                            if (colout[ix])
+                                __builtin_nontemporal_store(v[ix], (PR_GLOBAL T *)(obase + rowoff[iy] + colx[ix]));
+                    } else {
+                        gst_nt_row<T, NXP>(obase + rowoff[iy], v);
+                    }
                 }
             }
         };
@@ -1976,16 +2015,20 @@ struct CoarseEntry {
 #define FINE_1B(T, DT, NXP, NY, BXT, BY, PD, NAME)                                                       \
     FineEntry{VariantInfo{NAME, DT, 2, BXT * NXP - 8, BY * NY - 8, NXP, BXT * BY, 1},                  \
               &fine_launch_1b<T, NXP, NY, BXT, BY, PD>}
-template <typename T, int NXP, int NY, int NW, int PD, int SEG>
+template <typename T, int NXP, int NY, int NW, int PD, int SEG, int XT = 0>
 void fine_launch_rows(const ItemDesc *items, int nitems, int nblocks, int jstep, hipStream_t s, int *occ)
 {
-    if (occ) return occupancy_of((rk4_step_rows<T, NXP, NY, NW, PD, SEG>), 64 * NW, occ);
-    hipLaunchKernelGGL((rk4_step_rows<T, NXP, NY, NW, PD, SEG>), dim3(nblocks), dim3(64 * NW), 0, s, items, nitems,
+    if (occ) return occupancy_of((rk4_step_rows<T, NXP, NY, NW, PD, SEG, XT>), 64 * NW, occ);
+    hipLaunchKernelGGL((rk4_step_rows<T, NXP, NY, NW, PD, SEG, XT>), dim3(nblocks), dim3(64 * NW), 0, s, items, nitems,
                        jstep);
 }
 #define FINE_ROWS(T, DT, NXP, NY, NW, PD, NAME)                                                          \
     FineEntry{VariantInfo{NAME, DT, 2, 64 * NXP, NW * NY - 8, NXP, 64 * NW, 1, 64 * NXP},              \
               &fine_launch_rows<T, NXP, NY, NW, PD, 64>}
+// x tiles of 64*NXP columns (output 64*NXP - 8) over rows of any length
+#define FINE_ROWSX(T, DT, NXP, NY, NW, PD, NAME)                                                         \
+    FineEntry{VariantInfo{NAME, DT, 2, 64 * NXP - 8, NW * NY - 8, 1, 64 * NW, 1, 0},                    \
+              &fine_launch_rows<T, NXP, NY, NW, PD, 64, 1>}
 // grid rows of 16 lanes, four side by side in a wavefront
 #define FINE_ROWS16(T, DT, NXP, NY, NW, PD, NAME)                                                        \
     FineEntry{VariantInfo{NAME, DT, 2, 16 * NXP, 4 * NW * NY - 8, NXP, 64 * NW, 1, 16 * NXP},          \
@@ -2043,9 +2086,7 @@ const FineEntry kFine[] = {
     // one barrier per plane, any radius
     FINE_1R(float, 1, 2, 2, 2, 24, 16, 2, "rk4r_f32_o4_t32x16_p2x2_d2"),
     // one barrier per plane, radius 1, 2-D tiles
-    FINE_1B(double, 2, 2, 2, 20, 20, 2, "rk4b_f64_t32x32_p2x2_d2"),
     FINE_1B(double, 2, 1, 2, 40, 20, 2, "rk4b_f64_t32x32_p1x2_d2"),
-    FINE_1B(float, 1, 1, 4, 40, 10, 2, "rk4b_f32_t32x32_p1x4_d2"),
     FINE_1B(float, 1, 2, 2, 36, 20, 2, "rk4b_f32_t64x32_p2x2_d2"),
     FINE_1B(float, 1, 2, 2, 28, 16, 2, "rk4b_f32_t48x24_p2x2_d2"),
     FINE_1B(float, 1, 2, 2, 28, 20, 2, "rk4b_f32_t48x32_p2x2_d2"),
@@ -2064,6 +2105,11 @@ const FineEntry kFine[] = {
     FINE_ROWS16(float, 1, 4, 1, 8, 2, "rk4s_f32_x64_y24_p4x1_w8"),
     FINE_ROWS16(float, 1, 4, 1, 12, 2, "rk4s_f32_x64_y40_p4x1_w12"),
     FINE_ROWS16(float, 1, 2, 1, 10, 2, "rk4s_f32_x32_y32_p2x1_w10"),
+    // x tiles of 64 columns (56 outputs) wrapped onto rows of any length
+    FINE_ROWSX(float, 1, 1, 3, 16, 2, "rk4x_f32_t56x40_p1x3_w16"),
+    FINE_ROWSX(float, 1, 1, 5, 8, 2, "rk4x_f32_t56x32_p1x5_w8"),
+    FINE_ROWSX(double, 2, 1, 2, 8, 2, "rk4x_f64_t56x8_p1x2_w8"),
+    FINE_ROWSX(double, 2, 1, 3, 8, 2, "rk4x_f64_t56x16_p1x3_w8"),
     // whole rows, radius 2, two launches of two stages
     FINE_HALF_ROWS(double, 2, 2, 2, 16, 1, "rk4h_f64_o4_x128_y8_p2_w16_d1"),
     FINE_HALF_ROWS(float, 1, 2, 2, 16, 2, "rk4h_f32_o4_x128_y8_p2_w16"),

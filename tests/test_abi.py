@@ -231,7 +231,8 @@ def test_variant_registry():
     ((128, 128, 128), 2, 16, "rk4w_f64_x128_y8_p2x1_w16"),
     ((64, 64, 64), 2, 8, "rk4w_f64_x64_y16_p1x2_w12"),
     ((64, 64, 64), 2, 1, "rk4w_f64_x64_y8_p1x2_w8"),
-    ((40, 36, 20), 2, 4, "rk4b_f64_t32x32_p1x2_d2"),
+    ((40, 36, 20), 2, 4, "rk4x_f64_t56x8_p1x2_w8"),
+    ((160, 160, 160), 2, 8, "rk4x_f64_t56x16_p1x3_w8"),
     ((256, 256, 256), 1, 32, "rk4w_f32_x256_y8_p4x2_w8"),
     ((128, 128, 128), 1, 136, "rk4w_f32_x128_y16_p2x2_w12"),
     ((128, 128, 128), 1, 1, "rk4w_f32_x128_y8_p2x2_w8"),
@@ -242,14 +243,16 @@ def test_variant_registry():
     ((48, 48, 48), 2, 8, "rk4s_f64_x48_y24_p3x1_w8"),
     ((32, 32, 32), 2, 4, "rk4s_f64_x32_y32_p2x1_w10"),
     ((32, 32, 32), 1, 16, "rk4s_f32_x32_y32_p2x1_w10"),
-    ((80, 60, 40), 1, 16, "rk4b_f32_t48x32_p2x2_d2"),
+    ((80, 60, 40), 1, 16, "rk4x_f32_t56x40_p1x3_w16"),
+    ((192, 60, 40), 1, 16, "rk4b_f32_t64x32_p2x2_d2"),
     ((512, 512, 512), 1, 32, "rk4b_f32_t64x32_p2x2_d2"),
-    ((37, 29, 23), 1, 2, "rk4b_f32_t32x32_p1x4_d2"),
+    ((37, 29, 23), 1, 2, "rk4x_f32_t56x40_p1x3_w16"),
 ])
 def test_builtin_fine_kernel_choice(n3, dtype, batch, name):
     """Host logic, no device: the built-in F kernel for a grid (whole rows for
-    n_x = 64/128/256, 16-lane rows for n_x = 32/48/96, as measured; for other
-    FP32 grids the 2-D tile that computes the fewest points per output
+    n_x = 64/128/256, 16-lane rows for n_x = 32/48/96, as measured; other
+    widths: x-tiled rows, except FP32 rows whose n_x is a multiple of 64,
+    which take the 2-D tile that computes the fewest points per output
     point)."""
     import paper_1409_8563_amd as pr
     p = W.small_problem(n=n3, P=2, nf=4)
@@ -258,9 +261,10 @@ def test_builtin_fine_kernel_choice(n3, dtype, batch, name):
 
 
 def test_fp32_tile_choice_minimises_computed_points():
-    """For even FP32 grids without a whole-row kernel the chosen tile has the
-    fewest computed points per output point (4-point halo per side) among the
-    four two-point tiles."""
+    """FP32 grids without a whole-row kernel: where n_x is a multiple of 64
+    the chosen 2-D tile has the fewest computed points per output point (a
+    4-point halo per side) among the four two-point tiles; every other width
+    takes the x-tiled rows."""
     import paper_1409_8563_amd as pr
     cands = {v["name"]: v for v in pr.variants(0)
              if v["name"] in ("rk4b_f32_t64x32_p2x2_d2", "rk4b_f32_t64x24_p2x2_d2",
@@ -271,15 +275,19 @@ def test_fp32_tile_choice_minimises_computed_points():
         tx, ty = v["tile"]
         return (-(-nx // tx) * (tx + 8) / nx) * (-(-ny // ty) * (ty + 8) / ny)
 
-    for nx in range(8, 200, 6):
-        for ny in (10, 24, 48, 72, 100):
-            if nx in (32, 48, 64, 96, 128, 256):
-                continue
+    for nx in (192, 320, 384, 448, 512, 576, 640):
+        for ny in (10, 24, 48, 72, 100, 200):
             p = W.small_problem(n=(nx, ny, 12), P=2, nf=4)
             p.flags |= W.ALLOW_UNSTABLE
             got = pr.sweep_kernel_variant(p, 1, 4, 0)
             assert got in cands, (nx, ny, got)
             assert waste(cands[got], nx, ny) <= min(waste(v, nx, ny) for v in cands.values()) * (1 + 1e-12)
+    for nx in range(8, 260, 6):
+        if nx in (32, 48, 64, 96, 128, 256) or nx % 64 == 0:
+            continue
+        p = W.small_problem(n=(nx, 40, 12), P=2, nf=4)
+        p.flags |= W.ALLOW_UNSTABLE
+        assert pr.sweep_kernel_variant(p, 1, 4, 0) == "rk4x_f32_t56x40_p1x3_w16", nx
 
 
 def test_whole_row_variant_rejects_other_nx():
@@ -430,7 +438,7 @@ def test_autotune_cache_round_trip(tmp_path):
     p = W.small_problem(n=(40, 36, 20), P=2, nf=4)
     p.flags |= W.ALLOW_UNSTABLE
     default = pr.sweep_kernel_variant(p, 1, 4, 0)
-    tuned = "rk4b_f32_t32x32_p1x4_d2"
+    tuned = "rk4x_f32_t56x32_p1x5_w8"
     assert default != tuned
     src = tmp_path / "tune.json"
     src.write_text(json.dumps({"format": "pr-autotune-1", "entries": [

@@ -134,6 +134,36 @@ def test_fine_variants_bitwise_identical(pr, dtype, order):
 
 
 @pytest.mark.parametrize("dtype", [1, 2])
+@pytest.mark.parametrize("n3", [(131, 45, 17), (7, 9, 11), (200, 8, 5), (57, 100, 6), (112, 41, 3)])
+def test_fine_x_tiled_rows_bitwise_and_oracle(pr, orc, dtype, n3):
+    """The x-tiled row kernels (x tiles of 64 columns with a 4-column halo,
+    wrapped onto rows of any length) give the bits of the unfused reference
+    on ragged widths, on rows shorter than one tile (columns held twice),
+    on fewer rows than a tile and on z shorter than the pipeline; and they
+    follow the oracle."""
+    import torch
+    tdt = torch.float64 if dtype == 2 else torch.float32
+    p = W.small_problem(n=n3, a=(0.7, -0.45, 0.3), nu0=0.002, P=2, nf=64)
+    u0 = W.random_field(p.n, 150)
+    u = cuda(u0, tdt)
+    xt = [v["index"] for v in pr.variants(0) if v["name"].startswith("rk4x_") and v["dtype"] == dtype]
+    assert xt
+    outs = {}
+    try:
+        for v in [1] + xt:
+            say("x-tiled variant", v, dtype, n3)
+            pr.set_kernel_variant(v, 0)
+            outs[v] = pr.fine_sweep(p, u, 3, 3)
+    finally:
+        pr.set_kernel_variant(0, 0)
+    for v, o in outs.items():
+        assert torch.equal(o, outs[1]), v
+    ref = orc.fine_steps(p, 3, 3, host(u).reshape(p.n[2], p.n[1], p.n[0]))
+    got = host(outs[xt[0]]).reshape(ref.shape)
+    assert rel_l2(got, ref) <= (FP64_TOL if dtype == 2 else FP32_TOL)
+
+
+@pytest.mark.parametrize("dtype", [1, 2])
 @pytest.mark.parametrize("n3,order", [((128, 52, 21), 2), ((64, 37, 19), 2), ((256, 20, 9), 2), ((128, 8, 5), 2),
                                       ((96, 52, 21), 2), ((48, 37, 19), 2), ((48, 8, 5), 2), ((96, 100, 6), 2),
                                       ((32, 29, 13), 2), ((32, 8, 5), 2), ((64, 70, 9), 2),
@@ -541,6 +571,10 @@ def test_multi_instance_launch_groups(pr, orc):
                           (pr.PR_MODE_TIMED, probs), (0, skip_early), (pipe, probs),
                           (pipe | pr.PR_MODE_GRAPH, skip_only), (pipe | pr.PR_MODE_PIPELINE_GROUPS(3), probs)):
             say("launch groups", mode, extra, ps[0].flags)
+            # built-in kernel choices: a tuned table (from the previous round of
+            # this loop) may pick one kernel that serves every grid, which
+            # merges the groups
+            pr.autotune_clear()
             plan = pr.Plan(ps, mode | extra)
             groups = plan.fine_groups()
             assert len(groups) == 2 and sorted(g[2] for g in groups) == [1, 2], groups
