@@ -549,22 +549,56 @@ Choice pick_fine(const pr_problem &p, int dtype, int batch)
     return c;
 }
 
+// The coarse variant of a list that computes the fewest points for the
+// grid (the x-tiled Euler rows skip steps per wavefront like the RK4 rows;
+// S = 4 steps, halo 4).
+int cheapest_coarse_rows(const pr_problem &p, std::initializer_list<const char *> names)
+{
+    int best_v = -1;
+    double best = 1e300;
+    for (const char *nm : names) {
+        const int v = find_coarse(nm);
+        const VariantInfo *vi = pr::coarse_variant(v);
+        if (!vi) continue;
+        const double c = fine_tile_cost(vi, true, p);
+        if (c < best * (1 - 1e-12)) {
+            best = c;
+            best_v = v;
+        }
+    }
+    return best_v;
+}
+
+// Built-in G for one grid: whole rows where a kernel exists; FP64 otherwise
+// x-tiled rows (faster than the 2-D tiles on every cube measured, n = 40 ..
+// 512); FP32 the 2-D tile where n_x is a multiple of 32 up to 128 (whose
+// 32-wide tiles cover the row exactly: faster at 64 and 96), else x-tiled
+// rows (faster at 40, 48, 100, 160, 200, 384, 512).
 int pick_coarse_default(const pr_problem &p, int dtype)
 {
-    const bool even = p.n[0] % 2 == 0;
     const int nx = p.n[0];
-    const char *name;
-    if (dtype == PR_FP64)
-        name = nx == 128 ? "euler4w_f64_x128_y8_p2x1_w16"
-               : nx == 64 ? "euler4w_f64_x64_y8_p1x1_w16"
-               : even     ? "euler4b_f64_t32x32_p2x2_d2"
-                          : "euler4b_f64_t32x32_p1x4_d2";
-    else
-        name = nx == 256 ? "euler4w_f32_x256_y8_p4x1_w16"
-               : nx == 128 ? "euler4w_f32_x128_y8_p2x1_w16"
-               : even      ? "euler4b_f32_t32x32_p2x2_d2"
-                           : "euler4b_f32_t32x32_p1x4_d2";
-    return find_coarse(name);
+    if (dtype == PR_FP64) {
+        if (nx == 128) return find_coarse("euler4w_f64_x128_y8_p2x1_w16");
+        if (nx == 64) return find_coarse("euler4w_f64_x64_y8_p1x1_w16");
+        return find_coarse("euler4x_f64_t56x24_p1x2_w16");
+    }
+    if (nx == 256) return find_coarse("euler4w_f32_x256_y8_p4x1_w16");
+    if (nx == 128) return find_coarse("euler4w_f32_x128_y8_p2x1_w16");
+    if (nx % 32 == 0 && nx < 128) return find_coarse("euler4b_f32_t32x32_p2x2_d2");
+    // three rows per wavefront (more work per barrier) beyond 64 rows; on
+    // shorter grids the tile height that fits n_y best
+    if (p.n[1] > 64) return find_coarse("euler4x_f32_t56x40_p1x3_w16");
+    return cheapest_coarse_rows(p, {"euler4x_f32_t56x24_p1x2_w16", "euler4x_f32_t56x40_p1x3_w16"});
+}
+
+// Built-in G for instances of different widths in one plan (one launch per
+// slice boundary covers all of them): FP32 on even widths the 2-D tile
+// (measured best on the uneven batch of 48..128 cubes: chain 84 ms against
+// 90-107 ms for x-tiled rows), otherwise x-tiled rows.
+int pick_coarse_mixed(int dtype, bool all_even)
+{
+    if (dtype == PR_FP64) return find_coarse("euler4x_f64_t56x24_p1x2_w16");
+    return find_coarse(all_even ? "euler4b_f32_t32x32_p2x2_d2" : "euler4x_f32_t56x40_p1x3_w16");
 }
 
 Choice pick_coarse(const pr_problem &p, int dtype, int batch)
@@ -1806,8 +1840,7 @@ int pr_plan_create(const pr_problem *probs, int32_t ninst, int32_t mode, void *w
     }
     // G: one fused variant for all instances (the chain's launches are per
     // slice boundary): the choice for instance 0 if it applies to every
-    // instance, else the tiled default for a generic n_x, even if every
-    // instance has an even n_x (two x points per thread), else odd
+    // instance, else the built-in choice for instances of different widths
     const Choice cch = pick_coarse(coarse_grid(probs[0]), pl->dtype, ninst);
     int cv = cch.v;
     bool cok = cv >= 1;
@@ -1816,9 +1849,7 @@ int pr_plan_create(const pr_problem *probs, int32_t ninst, int32_t mode, void *w
         cok = cok && coarse_applicable(cv, pl->dtype, coarse_grid(probs[i]));
         all_even_c = all_even_c && coarse_grid(probs[i]).n[0] % 2 == 0;
     }
-    pr_problem generic_c = coarse_grid(probs[0]);
-    generic_c.n[0] = all_even_c ? 2 : 3;
-    if (!cok) cv = g_coarse_forced ? -1 : pick_coarse_default(generic_c, pl->dtype);
+    if (!cok) cv = g_coarse_forced ? -1 : pick_coarse_mixed(pl->dtype, all_even_c);
     if (cv < 1) {
         delete pl;
         return fail(PR_EUNSUPPORTED, "forced kernel variant does not apply to every instance");

@@ -1678,13 +1678,15 @@ __global__ void __launch_bounds__(BXT *BY)
 // LDS, y halo of S rows per side, stages skipped per wavefront near the tile
 // edge) with the z pipeline of euler_chunk_fused1b.
 // ---------------------------------------------------------------------------
-template <typename T, int S, int NXP, int NY, int NW, int PD>
+template <typename T, int S, int NXP, int NY, int NW, int PD, int XT = 0>
 __global__ void __launch_bounds__(64 * NW)
     euler_chunk_rows(const ItemDesc *__restrict__ items, int nitems, int chunk)
 {
     static_assert(6 % PD == 0, "prefetch depth must divide the unroll");
     constexpr int H = S;
-    constexpr int NX = 64 * NXP;
+    constexpr int NX = 64 * NXP;          // x extent of a wavefront (the whole row unless XT)
+    constexpr int HX = XT ? H : 0;        // x halo of an x tile
+    constexpr int TXT = NX - 2 * HX;      // output columns of an x tile
     constexpr int EY = NW * NY, TY = EY - 2 * H;
     constexpr int L = 3;                  // z-ring length
     constexpr int U = 6;                  // unroll: ring phase and LDS slot parity
@@ -1695,13 +1697,19 @@ __global__ void __launch_bounds__(64 * NW)
     const int lb = xcd_remap((int)blockIdx.x, (int)gridDim.x);
     const ItemDesc &it = items[find_item(items, nitems, lb)];
     const int nchunks = (it.nsteps + S - 1) / S;
-    if (chunk >= nchunks || it.nx != NX) return;
+    if (chunk >= nchunks || (!XT && it.nx != NX)) return;
     const int local = lb - it.block_begin;
     if (local < 0 || local >= it.nblocks) return;
 
-    const int ny = it.ny, nz = it.nz;
-    const int tyt = local % it.tiles_y;
-    const int zc = local / it.tiles_y;
+    const int nx = XT ? it.nx : NX, ny = it.ny, nz = it.nz;
+    int txt = 0, rest = local;
+    if constexpr (XT) {
+        txt = local % it.tiles_x;
+        rest = local / it.tiles_x;
+    }
+    const int tyt = rest % it.tiles_y;
+    const int zc = rest / it.tiles_y;
+    const int x0 = txt * TXT;
     const int y0 = tyt * TY;
     const int z0 = zc * it.tz;
     const int zend = min(z0 + it.tz, nz);
@@ -1721,10 +1729,21 @@ __global__ void __launch_bounds__(64 * NW)
 #pragma unroll
     for (int iy = 0; iy < NY; ++iy) {
         const int ry = ry0 + iy;
-        rowoff[iy] = wrapi(y0 - H + ry, ny) * NX + cx0;
+        rowoff[iy] = wrapi(y0 - H + ry, ny) * nx + (XT ? 0 : cx0);
         rowout[iy] = (ry >= H) && (ry < H + TY) && (y0 + ry - H < ny);
     }
-    const int nxy = NX * ny;
+    // x tiles: as in rk4_step_rows (S steps reach S columns into the halo)
+    int colx[XT ? NXP : 1];
+    bool colout[XT ? NXP : 1];
+    if constexpr (XT) {
+#pragma unroll
+        for (int ix = 0; ix < NXP; ++ix) {
+            const int c = cx0 + ix;
+            colx[ix] = wrapi(x0 - HX + c, nx);
+            colout[ix] = (c >= HX) && (c < HX + TXT) && (x0 + c - HX < nx);
+        }
+    }
+    const int nxy = nx * ny;
 
     Wts<T, 1> w[S];
     T dts[S];
@@ -1744,9 +1763,14 @@ __global__ void __launch_bounds__(64 * NW)
         const T *base = src + (size_t)wrapi(p, nz) * nxy;
 #pragma unroll
         for (int iy = 0; iy < NY; ++iy) {
-            const Vec<T, NXP> v = gld<Vec<T, NXP>>(base + rowoff[iy]);
+            if constexpr (XT) {
 #pragma unroll
-            for (int ix = 0; ix < NXP; ++ix) dstp[iy][ix] = v.v[ix];
+                for (int ix = 0; ix < NXP; ++ix) dstp[iy][ix] = *(const PR_GLOBAL T *)(base + rowoff[iy] + colx[ix]);
+            } else {
+                const Vec<T, NXP> v = gld<Vec<T, NXP>>(base + rowoff[iy]);
+#pragma unroll
+                for (int ix = 0; ix < NXP; ++ix) dstp[iy][ix] = v.v[ix];
+            }
         }
     };
 
@@ -1819,10 +1843,16 @@ __global__ void __launch_bounds__(64 * NW)
 #pragma unroll
                             for (int iy = 0; iy < NY; ++iy) {
                                 if (rowout[iy]) {
-                                    Vec<T, NXP> v;
+                                    if constexpr (XT) {
 #pragma unroll
-                                    for (int ix = 0; ix < NXP; ++ix) v.v[ix] = res[iy][ix];
-                                    gst<Vec<T, NXP>>(obase + rowoff[iy], v);
+                                        for (int ix = 0; ix < NXP; ++ix)
+                                            if (colout[ix]) *(PR_GLOBAL T *)(obase + rowoff[iy] + colx[ix]) = res[iy][ix];
+                                    } else {
+                                        Vec<T, NXP> v;
+#pragma unroll
+                                        for (int ix = 0; ix < NXP; ++ix) v.v[ix] = res[iy][ix];
+                                        gst<Vec<T, NXP>>(obase + rowoff[iy], v);
+                                    }
                                 }
                             }
                         }
@@ -2063,16 +2093,20 @@ void fine_launch_half_rows(const ItemDesc *items, int nitems, int nblocks, int j
 #define FINE_HALF_ROWS(T, DT, R, NXP, NW, PD, NAME)                                                      \
     FineEntry{VariantInfo{NAME, DT, 2 * R, 64 * NXP, NW - 4 * R, NXP, 64 * NW, 1, 64 * NXP, 2},        \
               &fine_launch_half_rows<T, R, NXP, NW, PD>}
-template <typename T, int S, int NXP, int NY, int NW, int PD>
+template <typename T, int S, int NXP, int NY, int NW, int PD, int XT = 0>
 void coarse_launch_rows(const ItemDesc *items, int nitems, int nblocks, int chunk, hipStream_t s, int *occ)
 {
-    if (occ) return occupancy_of((euler_chunk_rows<T, S, NXP, NY, NW, PD>), 64 * NW, occ);
-    hipLaunchKernelGGL((euler_chunk_rows<T, S, NXP, NY, NW, PD>), dim3(nblocks), dim3(64 * NW), 0, s, items, nitems,
-                       chunk);
+    if (occ) return occupancy_of((euler_chunk_rows<T, S, NXP, NY, NW, PD, XT>), 64 * NW, occ);
+    hipLaunchKernelGGL((euler_chunk_rows<T, S, NXP, NY, NW, PD, XT>), dim3(nblocks), dim3(64 * NW), 0, s, items,
+                       nitems, chunk);
 }
 #define COARSE_ROWS(T, DT, S, NXP, NY, NW, PD, NAME)                                                     \
     CoarseEntry{VariantInfo{NAME, DT, 0, 64 * NXP, NW * NY - 2 * S, NXP, 64 * NW, S, 64 * NXP},         \
                 &coarse_launch_rows<T, S, NXP, NY, NW, PD>}
+// x tiles of 64*NXP columns (output 64*NXP - 2S) over rows of any length
+#define COARSE_ROWSX(T, DT, S, NXP, NY, NW, PD, NAME)                                                    \
+    CoarseEntry{VariantInfo{NAME, DT, 0, 64 * NXP - 2 * S, NW * NY - 2 * S, 1, 64 * NW, S, 0},          \
+                &coarse_launch_rows<T, S, NXP, NY, NW, PD, 1>}
 #define COARSE_1B(T, DT, S, NXP, NY, BXT, BY, PD, NAME)                                                   \
     CoarseEntry{VariantInfo{NAME, DT, 0, BXT * NXP - 2 * S, BY * NY - 2 * S, NXP, BXT * BY, S},          \
                 &coarse_launch_1b<T, S, NXP, NY, BXT, BY, PD>}
@@ -2129,6 +2163,10 @@ const CoarseEntry kCoarse[] = {
     COARSE_ROWS(double, 2, 4, 1, 1, 16, 2, "euler4w_f64_x64_y8_p1x1_w16"),
     COARSE_ROWS(float, 1, 4, 4, 1, 16, 2, "euler4w_f32_x256_y8_p4x1_w16"),
     COARSE_ROWS(float, 1, 4, 2, 1, 16, 2, "euler4w_f32_x128_y8_p2x1_w16"),
+    // x tiles of 64 columns (56 outputs) wrapped onto rows of any length
+    COARSE_ROWSX(double, 2, 4, 1, 2, 16, 2, "euler4x_f64_t56x24_p1x2_w16"),
+    COARSE_ROWSX(float, 1, 4, 1, 2, 16, 2, "euler4x_f32_t56x24_p1x2_w16"),
+    COARSE_ROWSX(float, 1, 4, 1, 3, 16, 2, "euler4x_f32_t56x40_p1x3_w16"),
 };
 
 constexpr int kNumFine = (int)(sizeof(kFine) / sizeof(kFine[0]));

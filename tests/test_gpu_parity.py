@@ -134,6 +134,35 @@ def test_fine_variants_bitwise_identical(pr, dtype, order):
 
 
 @pytest.mark.parametrize("dtype", [1, 2])
+@pytest.mark.parametrize("n3", [(131, 45, 17), (7, 9, 11), (200, 8, 5), (57, 100, 6)])
+def test_coarse_x_tiled_rows_bitwise_and_oracle(pr, orc, dtype, n3):
+    """The x-tiled Euler kernels (4 steps per launch, x tiles with a
+    4-column halo wrapped onto rows of any length) give the bits of the
+    unfused reference, including a partial last chunk, and follow the
+    oracle."""
+    import torch
+    tdt = torch.float64 if dtype == 2 else torch.float32
+    p = W.small_problem(n=n3, a=(0.3, -0.2, 0.0), nu0=0.0005, P=1, nc=64)
+    u0 = W.random_field(p.n, 151)
+    u = cuda(u0, tdt)
+    xt = [v["index"] for v in pr.variants(1) if v["name"].startswith("euler4x_") and v["dtype"] == dtype]
+    assert xt
+    outs = {}
+    try:
+        for v in [1] + xt:
+            say("x-tiled coarse variant", v, dtype, n3)
+            pr.set_kernel_variant(0, v)
+            outs[v] = pr.coarse_sweep(p, u, 2, 11)
+    finally:
+        pr.set_kernel_variant(0, 0)
+    for v, o in outs.items():
+        assert torch.equal(o, outs[1]), v
+    ref = orc.coarse_steps(p, 2, 11, host(u).reshape(p.n[2], p.n[1], p.n[0]))
+    got = host(outs[xt[0]]).reshape(ref.shape)
+    assert rel_l2(got, ref) <= (FP64_TOL if dtype == 2 else FP32_TOL)
+
+
+@pytest.mark.parametrize("dtype", [1, 2])
 @pytest.mark.parametrize("n3", [(131, 45, 17), (7, 9, 11), (200, 8, 5), (57, 100, 6), (112, 41, 3)])
 def test_fine_x_tiled_rows_bitwise_and_oracle(pr, orc, dtype, n3):
     """The x-tiled row kernels (x tiles of 64 columns with a 4-column halo,
