@@ -571,16 +571,22 @@ int cheapest_coarse_rows(const pr_problem &p, std::initializer_list<const char *
 
 // Built-in G for one grid: whole rows where a kernel exists; FP64 otherwise
 // x-tiled rows (faster than the 2-D tiles on every cube measured, n = 40 ..
-// 512); FP32 the 2-D tile where n_x is a multiple of 32 up to 128 (whose
-// 32-wide tiles cover the row exactly: faster at 64 and 96), else x-tiled
-// rows (faster at 40, 48, 100, 160, 200, 384, 512).
+// 512) except on narrow rows; FP32 the 2-D tile where n_x is a multiple of
+// 32 up to 128 (whose 32-wide tiles cover the row exactly: faster at 64 and
+// 96), else x-tiled rows (faster at 40, 48, 100, 160, 200, 384, 512).
 int pick_coarse_default(const pr_problem &p, int dtype)
 {
     const int nx = p.n[0];
     if (dtype == PR_FP64) {
         if (nx == 128) return find_coarse("euler4w_f64_x128_y8_p2x1_w16");
         if (nx == 64) return find_coarse("euler4w_f64_x64_y8_p1x1_w16");
-        return find_coarse("euler4x_f64_t56x24_p1x2_w16");
+        // x-tiled rows unless their 64-column tiles compute far more points
+        // than the 32-wide 2-D tiles (narrow rows such as 32): per computed
+        // point they ran about a quarter faster
+        const int xt = find_coarse("euler4x_f64_t56x24_p1x2_w16");
+        const int tiled = find_coarse(nx % 2 == 0 ? "euler4b_f64_t32x32_p2x2_d2" : "euler4b_f64_t32x32_p1x4_d2");
+        const VariantInfo *vx = pr::coarse_variant(xt), *vt = pr::coarse_variant(tiled);
+        return 0.8 * fine_tile_cost(vx, true, p) <= fine_tile_cost(vt, false, p) ? xt : tiled;
     }
     if (nx == 256) return find_coarse("euler4w_f32_x256_y8_p4x1_w16");
     if (nx == 128) return find_coarse("euler4w_f32_x128_y8_p2x1_w16");

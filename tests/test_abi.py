@@ -265,6 +265,7 @@ def test_builtin_fine_kernel_choice(n3, dtype, batch, name):
     ((64, 64, 64), 2, "euler4w_f64_x64_y8_p1x1_w16"),
     ((256, 256, 256), 2, "euler4x_f64_t56x24_p1x2_w16"),
     ((37, 29, 23), 2, "euler4x_f64_t56x24_p1x2_w16"),
+    ((32, 32, 32), 2, "euler4b_f64_t32x32_p2x2_d2"),
     ((256, 256, 256), 1, "euler4w_f32_x256_y8_p4x1_w16"),
     ((128, 128, 128), 1, "euler4w_f32_x128_y8_p2x1_w16"),
     ((96, 96, 96), 1, "euler4b_f32_t32x32_p2x2_d2"),
@@ -274,7 +275,8 @@ def test_builtin_fine_kernel_choice(n3, dtype, batch, name):
 def test_builtin_coarse_kernel_choice(n3, dtype, name):
     """Host logic, no device: the built-in G kernel for a grid (whole rows
     where a kernel exists; FP32 2-D tiles where 32-wide tiles cover the row
-    up to 128; x-tiled rows otherwise)."""
+    up to 128; FP64 2-D tiles on rows too narrow for 64-column x tiles;
+    x-tiled rows otherwise)."""
     import paper_1409_8563_amd as pr
     p = W.small_problem(n=n3, P=2, nf=4)
     p.flags |= W.ALLOW_UNSTABLE
