@@ -503,8 +503,7 @@ int pick_fine_default(const pr_problem &p, int dtype, int batch)
         if (order == 2 && p.n[0] != 128 && p.n[0] != 64 && p.n[0] != 48 && p.n[0] != 32)
             return cheapest_tile(p, {"rk4x_f64_t56x8_p1x2_w8", "rk4x_f64_t56x16_p1x3_w8"}, true);
         name = order == 4 ? (p.n[0] == 128 ? "rk4h_f64_o4_x128_y8_p2_w16_d1"
-                             : even          ? "rk4_f64_o4_t32x16_p2x1"
-                                             : "rk4_f64_o4_t24x8_p1x1")
+                                             : "rk4hx_f64_o4_t120x8_p2_w16_d1")
                : p.n[0] == 128 ? "rk4w_f64_x128_y8_p2x1_w16"
                : p.n[0] == 64  ? (batch >= 4 ? "rk4w_f64_x64_y16_p1x2_w12" : "rk4w_f64_x64_y8_p1x2_w8")
                : p.n[0] == 48  ? "rk4s_f64_x48_y24_p3x1_w8"

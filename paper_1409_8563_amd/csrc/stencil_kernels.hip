@@ -1067,14 +1067,16 @@ __global__ void __launch_bounds__(64 * NW)
 // the iteration, into the slot of this iteration's parity, and one barrier
 // per plane orders the puts before the reads of the next iteration.
 // ---------------------------------------------------------------------------
-template <typename T, int R, int NXP, int NW, int PD, int HALF>
+template <typename T, int R, int NXP, int NW, int PD, int HALF, int XT = 0>
 __global__ void __launch_bounds__(64 * NW)
     rk4_half_rows(const ItemDesc *__restrict__ items, int nitems, int jstep)
 {
     static_assert(R >= 2 && R <= NXP, "radius 2..NXP: x neighbours in the adjacent lanes, and the plane that "
                                       "stage B reads next was computed an iteration earlier");
     constexpr int H = 2 * R;              // halo of two stages (rows and planes per side)
-    constexpr int NX = 64 * NXP;
+    constexpr int NX = 64 * NXP;          // x extent of a wavefront (the whole row unless XT)
+    constexpr int HX = XT ? H : 0;        // x halo of an x tile
+    constexpr int TXT = NX - 2 * HX;      // output columns of an x tile
     constexpr int EY = NW, TY = EY - 2 * H;
     constexpr int L = 6;                  // z-ring length: even, >= 2R + 1
     static_assert(L >= 2 * R + 1 && L % 2 == 0 && L % PD == 0, "ring length");
@@ -1083,17 +1085,23 @@ __global__ void __launch_bounds__(64 * NW)
 
     const int lb = xcd_remap((int)blockIdx.x, (int)gridDim.x);
     const ItemDesc &it = items[find_item(items, nitems, lb)];
-    if (jstep >= it.nsteps || it.nx != NX) return;
+    if (jstep >= it.nsteps || (!XT && it.nx != NX)) return;
     const int local = lb - it.block_begin;
     if (local < 0 || local >= it.nblocks) return;
 
-    const int ny = it.ny, nz = it.nz;
-    const int tyt = local % it.tiles_y;
-    const int zc = local / it.tiles_y;
+    const int nx = XT ? it.nx : NX, ny = it.ny, nz = it.nz;
+    int txt = 0, rest = local;
+    if constexpr (XT) {
+        txt = local % it.tiles_x;
+        rest = local / it.tiles_x;
+    }
+    const int tyt = rest % it.tiles_y;
+    const int zc = rest / it.tiles_y;
+    const int x0 = txt * TXT;
     const int y0 = tyt * TY;
     const int z0 = zc * it.tz;
     const int zend = min(z0 + it.tz, nz);
-    const int nxy = NX * ny;
+    const int nxy = nx * ny;
     const size_t npts = (size_t)nxy * nz;
 
     const T *src;
@@ -1105,8 +1113,20 @@ __global__ void __launch_bounds__(64 * NW)
     const int lane = (int)threadIdx.x & 63;
     const int wv = __builtin_amdgcn_readfirstlane((int)threadIdx.x >> 6);   // = tile row
     const int cx0 = lane * NXP;
-    const int rowoff = wrapi(y0 - H + wv, ny) * NX + cx0;
+    const int rowoff = wrapi(y0 - H + wv, ny) * nx + (XT ? 0 : cx0);
     const bool rowout = (wv >= H) && (wv < H + TY) && (y0 + wv - H < ny);
+    // x tiles, as in rk4_step_rows (two radius-R stages reach 2R columns
+    // into the halo)
+    int colx[XT ? NXP : 1];
+    bool colout[XT ? NXP : 1];
+    if constexpr (XT) {
+#pragma unroll
+        for (int ix = 0; ix < NXP; ++ix) {
+            const int c = cx0 + ix;
+            colx[ix] = wrapi(x0 - HX + c, nx);
+            colout[ix] = (c >= HX) && (c < HX + TXT) && (x0 + c - HX < nx);
+        }
+    }
     // stage s of the half can feed an output point only on rows sR .. EY-1-sR
     const bool act1 = wv >= R && wv < EY - R, act2 = wv >= 2 * R && wv < EY - 2 * R;
     int wn[2][R];   // wavefronts holding rows wv -/+ k (clamped; only active stages read them)
@@ -1140,9 +1160,15 @@ __global__ void __launch_bounds__(64 * NW)
 
     const T *in_src = HALF == 0 ? src : scr_y;
     auto load_plane = [&](const T *base, int pz, T(&d)[NXP]) {
-        const Vec<T, NXP> v = gld<Vec<T, NXP>>(base + (size_t)wrapi(pz, nz) * nxy + rowoff);
+        const T *row = base + (size_t)wrapi(pz, nz) * nxy + rowoff;
+        if constexpr (XT) {
 #pragma unroll
-        for (int ix = 0; ix < NXP; ++ix) d[ix] = v.v[ix];
+            for (int ix = 0; ix < NXP; ++ix) d[ix] = *(const PR_GLOBAL T *)(row + colx[ix]);
+        } else {
+            const Vec<T, NXP> v = gld<Vec<T, NXP>>(row);
+#pragma unroll
+            for (int ix = 0; ix < NXP; ++ix) d[ix] = v.v[ix];
+        }
     };
     auto put = [&](auto Bc, auto SLc, const T(&v)[NXP]) {
         constexpr int B = decltype(Bc)::value;
@@ -1241,13 +1267,28 @@ __global__ void __launch_bounds__(64 * NW)
                         vy.v[ix] = fmaT(cB, S[ix], in[SB][ix]);
                         va.v[ix] = fmaT(bB, S[ix], acc[SB][ix]);
                     }
-                    gst<Vec<T, NXP>>(scr_y + off, vy);
-                    gst<Vec<T, NXP>>(scr_a + off, va);
+                    if constexpr (XT) {
+#pragma unroll
+                        for (int ix = 0; ix < NXP; ++ix)
+                            if (colout[ix]) {
+                                *(PR_GLOBAL T *)(scr_y + off + colx[ix]) = vy.v[ix];
+                                *(PR_GLOBAL T *)(scr_a + off + colx[ix]) = va.v[ix];
+                            }
+                    } else {
+                        gst<Vec<T, NXP>>(scr_y + off, vy);
+                        gst<Vec<T, NXP>>(scr_a + off, va);
+                    }
                 } else {
                     Vec<T, NXP> v;
 #pragma unroll
                     for (int ix = 0; ix < NXP; ++ix) v.v[ix] = fmaT(bB, S[ix], acc[SB][ix]);
-                    gst_nt<Vec<T, NXP>>(dst + off, v);
+                    if constexpr (XT) {
+#pragma unroll
+                        for (int ix = 0; ix < NXP; ++ix)
+                            if (colout[ix]) __builtin_nontemporal_store(v.v[ix], (PR_GLOBAL T *)(dst + off + colx[ix]));
+                    } else {
+                        gst_nt<Vec<T, NXP>>(dst + off, v);
+                    }
                 }
             }
         };
@@ -2075,24 +2116,28 @@ void fine_launch_1r(const ItemDesc *items, int nitems, int nblocks, int jstep, h
               &fine_launch_1r<T, R, NXP, NY, BXT, BY, PD>}
 // Two launches per step (stages 1-2, then 3-4) through the item's scratch
 // fields; the occupancy is that of the fuller half.
-template <typename T, int R, int NXP, int NW, int PD>
+template <typename T, int R, int NXP, int NW, int PD, int XT = 0>
 void fine_launch_half_rows(const ItemDesc *items, int nitems, int nblocks, int jstep, hipStream_t s, int *occ)
 {
     if (occ) {
         int a = 1, b = 1;
-        occupancy_of((rk4_half_rows<T, R, NXP, NW, PD, 0>), 64 * NW, &a);
-        occupancy_of((rk4_half_rows<T, R, NXP, NW, PD, 1>), 64 * NW, &b);
+        occupancy_of((rk4_half_rows<T, R, NXP, NW, PD, 0, XT>), 64 * NW, &a);
+        occupancy_of((rk4_half_rows<T, R, NXP, NW, PD, 1, XT>), 64 * NW, &b);
         *occ = a < b ? a : b;
         return;
     }
-    hipLaunchKernelGGL((rk4_half_rows<T, R, NXP, NW, PD, 0>), dim3(nblocks), dim3(64 * NW), 0, s, items, nitems,
+    hipLaunchKernelGGL((rk4_half_rows<T, R, NXP, NW, PD, 0, XT>), dim3(nblocks), dim3(64 * NW), 0, s, items, nitems,
                        jstep);
-    hipLaunchKernelGGL((rk4_half_rows<T, R, NXP, NW, PD, 1>), dim3(nblocks), dim3(64 * NW), 0, s, items, nitems,
+    hipLaunchKernelGGL((rk4_half_rows<T, R, NXP, NW, PD, 1, XT>), dim3(nblocks), dim3(64 * NW), 0, s, items, nitems,
                        jstep);
 }
 #define FINE_HALF_ROWS(T, DT, R, NXP, NW, PD, NAME)                                                      \
     FineEntry{VariantInfo{NAME, DT, 2 * R, 64 * NXP, NW - 4 * R, NXP, 64 * NW, 1, 64 * NXP, 2},        \
               &fine_launch_half_rows<T, R, NXP, NW, PD>}
+// the same over x tiles of 64*NXP columns (output 64*NXP - 4R) on rows of any length
+#define FINE_HALF_ROWSX(T, DT, R, NXP, NW, PD, NAME)                                                     \
+    FineEntry{VariantInfo{NAME, DT, 2 * R, 64 * NXP - 4 * R, NW - 4 * R, 1, 64 * NW, 1, 0, 2},         \
+              &fine_launch_half_rows<T, R, NXP, NW, PD, 1>}
 template <typename T, int S, int NXP, int NY, int NW, int PD, int XT = 0>
 void coarse_launch_rows(const ItemDesc *items, int nitems, int nblocks, int chunk, hipStream_t s, int *occ)
 {
@@ -2113,9 +2158,8 @@ void coarse_launch_rows(const ItemDesc *items, int nitems, int nblocks, int chun
 
 // index 0 and 1 are reserved (automatic, unfused reference)
 const FineEntry kFine[] = {
-    // first fused form (four barriers per plane): fourth order on grids without a whole-row kernel
+    // first fused form (four barriers per plane), fourth order
     FINE_V(double, 2, 2, 2, 1, 24, 32, "rk4_f64_o4_t32x16_p2x1"),
-    FINE_V(double, 2, 2, 1, 1, 40, 24, "rk4_f64_o4_t24x8_p1x1"),
     FINE_V(float, 1, 2, 1, 2, 48, 16, "rk4_f32_o4_t32x16_p1x2"),
     // one barrier per plane, any radius
     FINE_1R(float, 1, 2, 2, 2, 24, 16, 2, "rk4r_f32_o4_t32x16_p2x2_d2"),
@@ -2147,6 +2191,7 @@ const FineEntry kFine[] = {
     // whole rows, radius 2, two launches of two stages
     FINE_HALF_ROWS(double, 2, 2, 2, 16, 1, "rk4h_f64_o4_x128_y8_p2_w16_d1"),
     FINE_HALF_ROWS(float, 1, 2, 2, 16, 2, "rk4h_f32_o4_x128_y8_p2_w16"),
+    FINE_HALF_ROWSX(double, 2, 2, 2, 16, 1, "rk4hx_f64_o4_t120x8_p2_w16_d1"),
 };
 
 const CoarseEntry kCoarse[] = {

@@ -133,6 +133,33 @@ def test_fine_variants_bitwise_identical(pr, dtype, order):
         assert torch.equal(o, base), v
 
 
+@pytest.mark.parametrize("dtype", [2])
+@pytest.mark.parametrize("n3", [(131, 45, 17), (7, 9, 11), (200, 20, 9), (57, 100, 6)])
+def test_fine_x_tiled_fourth_order_bitwise_and_oracle(pr, orc, dtype, n3):
+    """The FP64 fourth-order F over x tiles (two launches of two fused
+    radius-2 stages, 4-column x halo, rows of any length) gives the bits of
+    the unfused reference and follows the oracle."""
+    import torch
+    tdt = torch.float64 if dtype == 2 else torch.float32
+    p = W.small_problem(n=n3, a=(0.7, -0.45, 0.3), nu0=0.0005, P=2, nf=64, order=4)
+    u = cuda(W.random_field(p.n, 152), tdt)
+    xt = [v["index"] for v in pr.variants(0) if v["name"].startswith("rk4hx_") and v["dtype"] == dtype]
+    assert xt
+    outs = {}
+    try:
+        for v in [1] + xt:
+            say("x-tiled order-4 variant", v, dtype, n3)
+            pr.set_kernel_variant(v, 0)
+            outs[v] = pr.fine_sweep(p, u, 3, 3)
+    finally:
+        pr.set_kernel_variant(0, 0)
+    for v, o in outs.items():
+        assert torch.equal(o, outs[1]), v
+    ref = orc.fine_steps(p, 3, 3, host(u).reshape(p.n[2], p.n[1], p.n[0]))
+    got = host(outs[xt[0]]).reshape(ref.shape)
+    assert rel_l2(got, ref) <= (FP64_TOL if dtype == 2 else FP32_TOL)
+
+
 @pytest.mark.parametrize("dtype", [1, 2])
 @pytest.mark.parametrize("n3", [(131, 45, 17), (7, 9, 11), (200, 8, 5), (57, 100, 6)])
 def test_coarse_x_tiled_rows_bitwise_and_oracle(pr, orc, dtype, n3):
@@ -352,7 +379,8 @@ def test_parareal_every_iterate_against_oracle(pr, orc):
 def test_parareal_fourth_order_every_iterate_against_oracle(pr, orc, n3):
     """The paper's fourth-order F inside Parareal, K = 0..P, every slice state
     element by element against the oracle: on a 128-wide grid (whole-row
-    kernels, two launches per RK4 step) and on an odd grid (tiled kernel)."""
+    kernels, two launches per RK4 step) and on an odd grid (the same pair
+    over x tiles)."""
     p = W.small_problem(n=n3, a=(0.6, 0.9, -0.4), nu0=0.0005, P=3, nf=12, nc=6, order=4)
     u0 = W.random_field(p.n, 181)
     _, _, hist = orc.parareal(p, u0, K=p.P, history=True)
@@ -364,7 +392,7 @@ def test_parareal_fourth_order_every_iterate_against_oracle(pr, orc, n3):
             assert rel_l2(states[0][n], hist[K, n]) <= FP64_TOL, (K, n)
     plan = pr.Plan([p], pr.PR_MODE_FP64)
     fv = plan.kernel_variants()[0]
-    assert fv.startswith("rk4h_f64_o4") if n3[0] == 128 else fv.startswith("rk4_f64_o4"), fv
+    assert fv.startswith("rk4h_f64_o4") if n3[0] == 128 else fv.startswith("rk4hx_f64_o4"), fv
 
 
 def test_parareal_modes_bitwise_identical(pr):
