@@ -598,6 +598,44 @@ def test_multi_instance_whole_row_kernels(pr, orc):
         assert np.array_equal(one[0], got), i
 
 
+@pytest.mark.parametrize("mode", [0, 1])
+def test_multi_instance_x_tiled_rows(pr, orc, mode):
+    """Instances of different widths (40, 100, 131) in one plan whose F and G
+    run over x tiles: each launch covers items of different n_x (tiles per
+    row from each item); every instance equals its own single-instance solve
+    bitwise and, in FP64, the oracle."""
+    probs, u0s = [], []
+    for i, (n3, a, nu0, nf, nc) in enumerate([((40, 36, 20), (0.6, -0.4, 0.2), 0.002, 8, 8),
+                                              ((100, 30, 24), (-0.5, 0.7, 0.3), 0.001, 10, 16),
+                                              ((131, 20, 16), (0.4, 0.5, -0.6), 0.001, 12, 16)]):
+        p = W.small_problem(n=n3, a=a, nu0=nu0, P=3, nf=nf, nc=nc, K=2)
+        probs.append(p)
+        u0s.append(W.random_field(p.n, 290 + i))
+    dt = 2 if mode == pr.PR_MODE_FP64 else 1
+    xf = "rk4x_f64_t56x8_p1x2_w8" if dt == 2 else "rk4x_f32_t56x40_p1x3_w16"
+    xg = "euler4x_f64_t56x24_p1x2_w16" if dt == 2 else "euler4x_f32_t56x40_p1x3_w16"
+    fi = {v["name"]: v["index"] for v in pr.variants(0)}[xf]
+    gi = {v["name"]: v["index"] for v in pr.variants(1)}[xg]
+    singles = []
+    try:
+        pr.set_kernel_variant(fi, gi)
+        for i, p in enumerate(probs):
+            singles.append(_solve(pr, [p], [u0s[i]], mode)[0][0])
+        plan = pr.Plan(probs, mode)
+        assert plan.kernel_variants() == (xf, xg)
+        assert len(plan.fine_groups()) == 1
+        uT, _ = plan.solve([cuda(u) for u in u0s])
+    finally:
+        pr.set_kernel_variant(0, 0)
+    for i, p in enumerate(probs):
+        say("x-tiled multi-instance", mode, i)
+        got = host(uT[i])
+        assert np.array_equal(got, singles[i]), i
+        if mode == pr.PR_MODE_FP64:
+            U, _ = orc.parareal(p, u0s[i], K=p.K)
+            assert rel_l2(got, U[-1]) <= FP64_TOL, i
+
+
 def test_multi_instance_launch_groups(pr, orc):
     """Instances whose grids call for different F kernels (whole rows of a
     wavefront at n_x = 128, of 16 lanes at n_x = 48) run as separate launch
