@@ -208,7 +208,8 @@ def workload_solves(pr, W, torch, quick=False):
     Parareal (one F launch per slice and step) and the serial FP64 fine
     sweep (median of `reps` calls after one); and every form's result over
     the whole field for the accuracy check against the FP64 reference
-    computed in the CPU leg."""
+    computed in the CPU leg (for 256^3 also the FP32-sweep iterate after
+    each iteration)."""
     import numpy as np
 
     def timed(fn, reps, warm=1):
@@ -258,6 +259,20 @@ def workload_solves(pr, W, torch, quick=False):
             "note": "eager launches" if big else "replayed from a recorded HIP graph; the first call records it"}
         del plan
         torch.cuda.empty_cache()
+        if name == "c3_256_mixed":
+            # the FP32-sweep iterate after every iteration k (a solve stopped after k corrections
+            # computes the same iterate as the k-th of the full solve), for its error against the
+            # FP64 reference per iteration
+            its = {}
+            for k in range(1, p.K):
+                pk, _ = W.config(name, K=k)
+                plan = pr.Plan([pk], mode)
+                plan.solve([u0], uT=[uT], want_log=False)
+                its[k] = grab(uT)
+                del plan
+                torch.cuda.empty_cache()
+            its[p.K] = batched
+            rec["per_iteration"] = its
         if name in ("c2_128_fp64", "c3_256_mixed"):
             # the pipelined schedule (Section 2.2.1) in two slice groups
             plan = pr.Plan([p], mode | pr.PR_MODE_PIPELINED | pr.PR_MODE_PIPELINE_GROUPS(2))
@@ -424,6 +439,11 @@ def cpu_leg(p_main, u0_np, solves, budget_s=8.0):
                         sol.serial_fine_fft().ravel())
             entry["accuracy_vs_fp64_serial_fine"] = {
                 form: errs(rec["result"], fine_ref) for form, rec in solves[name]["forms"].items()}
+            if "per_iteration" in solves[name]:
+                entry["per_iteration_vs_fp64"] = [
+                    {"k": k, "vs_fp64_parareal": errs(res, sol.iterate_fft(k, p.P).ravel()),
+                     "vs_fp64_serial_fine": errs(res, fine_ref)}
+                    for k, res in sorted(solves[name]["per_iteration"].items())]
             del fine_ref
         per[name] = entry
         log("cpu leg", name, entry)
@@ -706,7 +726,8 @@ def main():
                                   "bitwise_equal_to_batched": pf["bitwise_equal_to_batched"]}
             if cpu is not None and name in cpu["per_workload"]:
                 c = cpu["per_workload"][name]
-                for key in ("reference", "accuracy_vs_fp64_parareal", "accuracy_vs_fp64_serial_fine"):
+                for key in ("reference", "accuracy_vs_fp64_parareal", "accuracy_vs_fp64_serial_fine",
+                            "per_iteration_vs_fp64"):
                     if key in c:
                         e[key] = c[key]
                 e["oracle_wall_s"] = {k: v for k, v in c.items() if k.startswith("threads_")}
