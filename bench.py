@@ -60,9 +60,12 @@ def measured_traffic(variant, workload):
 
 
 def kernel_of(variant):
-    """HIP kernel that a fused fine variant launches."""
+    """HIP kernel that a fine variant launches."""
+    if variant == "rk4_unfused_reference":
+        return "rk4_stage_ref"
     for prefix, kernel in (("rk4w_", "rk4_step_rows"), ("rk4s_", "rk4_step_rows"), ("rk4x_", "rk4_step_rows"),
-                           ("rk4b_", "rk4_step_fused1b"), ("rk4h_", "rk4_half_rows"), ("rk4r_", "rk4_step_fused1r"),
+                           ("rk4b_", "rk4_step_fused1b"), ("rk4h_", "rk4_half_rows"), ("rk4hx_", "rk4_half_rows"),
+                           ("rk4r_", "rk4_step_fused1r"),
                            ("rk4_", "rk4_step_fused")):
         if variant.startswith(prefix):
             return kernel
