@@ -2159,12 +2159,10 @@ void coarse_launch_rows(const ItemDesc *items, int nitems, int nblocks, int chun
 // index 0 and 1 are reserved (automatic, unfused reference)
 const FineEntry kFine[] = {
     // first fused form (four barriers per plane), fourth order
-    FINE_V(double, 2, 2, 2, 1, 24, 32, "rk4_f64_o4_t32x16_p2x1"),
     FINE_V(float, 1, 2, 1, 2, 48, 16, "rk4_f32_o4_t32x16_p1x2"),
     // one barrier per plane, any radius
     FINE_1R(float, 1, 2, 2, 2, 24, 16, 2, "rk4r_f32_o4_t32x16_p2x2_d2"),
     // one barrier per plane, radius 1, 2-D tiles
-    FINE_1B(double, 2, 1, 2, 40, 20, 2, "rk4b_f64_t32x32_p1x2_d2"),
     FINE_1B(float, 1, 2, 2, 36, 20, 2, "rk4b_f32_t64x32_p2x2_d2"),
     FINE_1B(float, 1, 2, 2, 28, 16, 2, "rk4b_f32_t48x24_p2x2_d2"),
     FINE_1B(float, 1, 2, 2, 28, 20, 2, "rk4b_f32_t48x32_p2x2_d2"),
@@ -2185,7 +2183,6 @@ const FineEntry kFine[] = {
     FINE_ROWS16(float, 1, 2, 1, 10, 2, "rk4s_f32_x32_y32_p2x1_w10"),
     // x tiles of 64 columns (56 outputs) wrapped onto rows of any length
     FINE_ROWSX(float, 1, 1, 3, 16, 2, "rk4x_f32_t56x40_p1x3_w16"),
-    FINE_ROWSX(float, 1, 1, 5, 8, 2, "rk4x_f32_t56x32_p1x5_w8"),
     FINE_ROWSX(double, 2, 1, 2, 8, 2, "rk4x_f64_t56x8_p1x2_w8"),
     FINE_ROWSX(double, 2, 1, 3, 8, 2, "rk4x_f64_t56x16_p1x3_w8"),
     // whole rows, radius 2, two launches of two stages

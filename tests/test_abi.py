@@ -461,7 +461,7 @@ def test_autotune_cache_round_trip(tmp_path):
     p = W.small_problem(n=(40, 36, 20), P=2, nf=4)
     p.flags |= W.ALLOW_UNSTABLE
     default = pr.sweep_kernel_variant(p, 1, 4, 0)
-    tuned = "rk4x_f32_t56x32_p1x5_w8"
+    tuned = "rk4b_f32_t48x24_p2x2_d2"
     assert default != tuned
     src = tmp_path / "tune.json"
     src.write_text(json.dumps({"format": "pr-autotune-1", "entries": [

@@ -35,7 +35,7 @@ def test_error_measures():
     ("rk4r_f32_o4_t32x16_p2x2_d2", "rk4_step_fused1r"),
     ("rk4h_f64_o4_x128_y8_p2_w16_d1", "rk4_half_rows"),
     ("rk4hx_f64_o4_t120x8_p2_w16_d1", "rk4_half_rows"),
-    ("rk4_f64_o4_t32x16_p2x1", "rk4_step_fused"),
+    ("rk4_f32_o4_t32x16_p1x2", "rk4_step_fused"),
     ("rk4_unfused_reference", "rk4_stage_ref"),
 ])
 def test_kernel_of(name, kernel):
