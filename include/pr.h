@@ -365,7 +365,7 @@ int pr_plan_autotune(pr_plan *plan, void *stream, int32_t *fine_variant, int32_t
  * the current device's architecture only.
  *   pr_autotune_save   write the table as JSON to `path` (HOST string)
  *   pr_autotune_load   merge the entries of such a file into the table;
- *                      entries naming a variant this build lacks are skipped;
+ *                      entries naming a variant the library lacks are skipped;
  *                      *loaded (HOST, may be NULL) receives the number merged
  *   pr_autotune_clear  empty the table
  * If the environment variable PR_AUTOTUNE_CACHE names a file, that file is

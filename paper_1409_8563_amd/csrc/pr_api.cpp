@@ -313,7 +313,7 @@ int find_coarse(const char *name)
 //   {"format": "pr-autotune-1", "entries": [
 //     {"arch": "gfx950", "which": 0, "n": [128, 128, 128], "dtype": 2, "order": 2,
 //      "batch": 16, "variant": "rk4w_f64_x128_y8_p2x1_w16", "blocks_per_cu": 0}, ...]}
-// Variants are stored by name; entries naming a variant this build does not
+// Variants are stored by name; entries naming a variant the library does not
 // have are skipped when loading.
 
 bool json_field(const std::string &obj, const char *key, size_t *pos)
